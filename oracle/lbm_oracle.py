@@ -1,0 +1,429 @@
+"""Plain FP64 CPU oracle for the general LBGK model of Shi, He and Guo
+("Lattice Boltzmann model for high-order nonlinear partial differential
+equations").
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this
+module: only the tests, the smoke check and the CPU-baseline leg of the
+benchmark use it.  It shares no code with the HIP library; it reads only the
+`Problem` descriptions of `paper_0907_1720_amd.workloads` (which carry no
+lattice Boltzmann arithmetic).
+
+What it computes, in the paper's order and notation:
+
+* Sec. II.B eq. (taus): the relaxation polynomials tau_2 .. tau_6.
+* Sec. II.C-F and Sec. III.C: beta_k = alpha_k / (dt^{k-1} tau_k), the
+  corrections A_40, A_50, A_60 and the auxiliary moments Pi_k0 as exact
+  antiderivatives (zero at phi = 0) of the integrands printed with eqs. (Pi4),
+  (Pi5), (Pi6).  All of this is exact rational arithmetic on the binary values
+  of the inputs; each coefficient is rounded to FP64 once.
+* Sec. III.A/B: scaled moments Pi_bar_0 = phi, Pi_bar_1 = Pi_1 / c,
+  Pi_bar_k = (Pi_k0 + beta_k Pi_k) / c^k and the equilibrium
+  f_eq = M_q^{-1} Pi_bar with the printed integer inverses (1/24, 1/720).
+* Sec. II.A eq. (LBE): BGK collision f* = f - (f - f_eq)/tau and streaming
+  f_j(x + e_j dx) = f*_j(x) with periodic wrap; phi = sum_j f_j (eq. moments).
+
+Readings where the paper is silent or inconsistent (all selectable):
+
+* am = 0 ("corrected", default): eq. (Pi5) and eq. (Pi6) are derived from the
+  unmodified Pi_40 / Pi_50; with A_40 != 0 the fourth moment carries an extra
+  A_40 phi that has to be propagated the same way beta_4 Pi_4 is.  The
+  corrected integrands add 5 A_40 Pi_1' to Pi_50, 15 A_40 (Pi_1')^2 +
+  6 A_50 Pi_1' to Pi_60, and A_60 gains 5 tau_2 tau_5 beta_2 A_40 / tau_6.
+  am = 1 uses the integrands exactly as printed.  The two agree whenever
+  beta_2 = 0.
+* Integration constants of Pi_k0 are zero (the closed forms of Sec. III.C
+  vanish at phi = 0).
+* Scheme 2 (Sec. IV, Examples 4.5-4.8) sets the top moment Pi_bar_{q-1} to 0.
+* Initial distribution f = f_eq(phi0).
+* Bounded domains (used only to pin the paper's tables): after each step the
+  outer boundary layers are reset from the exact solution, either to the
+  equilibrium (kind "eq") or by non-equilibrium extrapolation from the first
+  interior node (kind "nee").
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+from math import comb
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# exact polynomial arithmetic (ascending coefficient lists of Fractions)
+# ---------------------------------------------------------------------------
+
+Poly = List[Fraction]
+
+
+def _trim(p: Poly) -> Poly:
+    p = list(p)
+    while p and p[-1] == 0:
+        p.pop()
+    return p
+
+
+def poly(coeffs: Sequence[float]) -> Poly:
+    return _trim([Fraction(c) for c in coeffs])
+
+
+def padd(*ps: Poly) -> Poly:
+    n = max((len(p) for p in ps), default=0)
+    out = [Fraction(0)] * n
+    for p in ps:
+        for i, c in enumerate(p):
+            out[i] += c
+    return _trim(out)
+
+
+def pscale(p: Poly, s) -> Poly:
+    s = Fraction(s)
+    return _trim([c * s for c in p])
+
+
+def pmul(a: Poly, b: Poly) -> Poly:
+    if not a or not b:
+        return []
+    out = [Fraction(0)] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        if x == 0:
+            continue
+        for j, y in enumerate(b):
+            out[i + j] += x * y
+    return _trim(out)
+
+
+def ppow(p: Poly, n: int) -> Poly:
+    out: Poly = [Fraction(1)]
+    for _ in range(n):
+        out = pmul(out, p)
+    return out
+
+
+def pderiv(p: Poly) -> Poly:
+    return _trim([i * p[i] for i in range(1, len(p))])
+
+
+def pinteg(p: Poly) -> Poly:
+    """Antiderivative that vanishes at phi = 0."""
+    return _trim([Fraction(0)] + [c / (i + 1) for i, c in enumerate(p)])
+
+
+def pconst(c) -> Poly:
+    return _trim([Fraction(c)])
+
+
+def pval_exact(p: Poly, x: Fraction) -> Fraction:
+    acc = Fraction(0)
+    for c in reversed(p):
+        acc = acc * x + c
+    return acc
+
+
+# ---------------------------------------------------------------------------
+# Sec. II.B eq. (taus)
+# ---------------------------------------------------------------------------
+
+def relaxation_taus(tau) -> Dict[int, Fraction]:
+    t = Fraction(tau)
+    F = Fraction
+    return {
+        1: F(1),
+        2: -t + F(1, 2),
+        3: t ** 2 - t + F(1, 6),
+        4: -t ** 3 + F(3, 2) * t ** 2 - F(7, 12) * t + F(1, 24),
+        5: t ** 4 - 2 * t ** 3 + F(5, 4) * t ** 2 - F(1, 4) * t + F(1, 120),
+        6: -t ** 5 + F(5, 2) * t ** 4 - F(13, 6) * t ** 3 + F(3, 4) * t ** 2 - F(31, 360) * t + F(1, 720),
+    }
+
+
+# ---------------------------------------------------------------------------
+# Sec. III: velocity sets and the printed inverse moment matrices
+# ---------------------------------------------------------------------------
+
+VELOCITIES = (0, 1, -1, 2, -2, 3, -3)
+
+# M_5^{-1} = (1/24) * integer matrix (Sec. III.A)
+M5_INV_DEN = 24
+M5_INV_INT = (
+    (24, 0, -30, 0, 6),
+    (0, 16, 16, -4, -4),
+    (0, -16, 16, 4, -4),
+    (0, -2, -1, 2, 1),
+    (0, 2, -1, -2, 1),
+)
+
+# M_7^{-1} = (1/720) * integer matrix (Sec. III.B)
+M7_INV_DEN = 720
+M7_INV_INT = (
+    (720, 0, -980, 0, 280, 0, -20),
+    (0, 540, 540, -195, -195, 15, 15),
+    (0, -540, 540, 195, -195, -15, 15),
+    (0, -108, -54, 120, 60, -12, -6),
+    (0, 108, -54, -120, 60, 12, -6),
+    (0, 12, 4, -15, -5, 3, 1),
+    (0, -12, 4, 15, -5, -3, 1),
+)
+
+
+def inverse_moment_matrix(q: int):
+    """(integer matrix, denominator) of M_q^{-1} as printed."""
+    if q == 5:
+        return np.array(M5_INV_INT, dtype=np.float64), float(M5_INV_DEN)
+    if q == 7:
+        return np.array(M7_INV_INT, dtype=np.float64), float(M7_INV_DEN)
+    raise ValueError("only D1Q5 and D1Q7 are defined in the paper")
+
+
+def inverse_moment_matrix_exact(q: int):
+    ints, den = (M5_INV_INT, M5_INV_DEN) if q == 5 else (M7_INV_INT, M7_INV_DEN)
+    return [[Fraction(v, den) for v in row] for row in ints]
+
+
+# ---------------------------------------------------------------------------
+# model construction (once per problem)
+# ---------------------------------------------------------------------------
+
+class OracleModel:
+    """All per-problem quantities; exact values kept beside their FP64 roundings."""
+
+    def __init__(self):
+        self.q = 5
+        self.m = 1
+        self.e: np.ndarray = None
+        self.tau = 1.0
+        self.c = 1.0
+        self.scheme = 1
+        self.taus: Dict[int, Fraction] = {}
+        self.beta: Dict[int, Fraction] = {}
+        self.A: Dict[int, Fraction] = {}
+        self.Pi: Dict[int, Poly] = {}       # Pi_k, k = 1..6
+        self.Pi0: Dict[int, Poly] = {}      # Pi_k0, k = 2..q-1
+        # FP64 roundings used by the time step
+        self.Pi_f: Dict[int, np.ndarray] = {}
+        self.Pi0_f: Dict[int, np.ndarray] = {}
+        self.beta_f: Dict[int, float] = {}
+
+
+class SingularTau(ValueError):
+    pass
+
+
+def build_model(problem) -> OracleModel:
+    """Set up the LBGK model for one problem (Sec. II and Sec. III)."""
+    mdl = OracleModel()
+    m = problem.order()
+    q = problem.q if problem.q else (5 if m <= 4 else 7)
+    if q not in (5, 7) or q < m + 1:
+        raise ValueError(f"lattice D1Q{q} cannot carry an order-{m} equation (needs q >= m + 1)")
+    if not problem.tau > 0.5:
+        raise ValueError("tau must exceed 1/2")
+    mdl.q, mdl.m = q, m
+    mdl.e = np.array(VELOCITIES[:q], dtype=np.int64)
+    mdl.tau = float(problem.tau)
+    mdl.scheme = int(problem.scheme)
+    dx, dt = Fraction(problem.dx), Fraction(problem.dt)
+    mdl.c = problem.dx / problem.dt
+    corrected = int(problem.am) == 0
+
+    taus = relaxation_taus(problem.tau)
+    mdl.taus = taus
+
+    # Pi_k as given (k = 1..6); absent ones are zero
+    Pi = {k: poly(problem.pi[k]) if k < len(problem.pi) else [] for k in range(1, 7)}
+    mdl.Pi = Pi
+
+    # beta_k = alpha_k / (dt^{k-1} tau_k); zero where alpha_k = 0 (Remarks 2 and 4)
+    beta: Dict[int, Fraction] = {}
+    for k in range(2, 7):
+        a = Fraction(problem.alpha[k]) if k <= m else Fraction(0)
+        if a == 0 or not Pi[k]:
+            beta[k] = Fraction(0)
+            continue
+        if taus[k] == 0:
+            raise SingularTau(f"tau_{k} = 0 while alpha_{k} != 0")
+        beta[k] = a / (dt ** (k - 1) * taus[k])
+    mdl.beta = beta
+    t2, t3, t4, t5, t6 = (taus[k] for k in (2, 3, 4, 5, 6))
+    b2, b3, b4, b5 = beta[2], beta[3], beta[4], beta[5]
+
+    def _div(num: Fraction, den: Fraction, name: str) -> Fraction:
+        if num == 0:
+            return Fraction(0)
+        if den == 0:
+            raise SingularTau(f"{name} needs division by a vanishing relaxation polynomial")
+        return num / den
+
+    # corrections, Sec. II.D-F (also listed after eq. Pi30t60)
+    A40 = _div(t2 * (3 * t3 - t2 ** 2) * b2 ** 2, t4, "A_40") if q > 4 else Fraction(0)
+    A50 = _div((4 * t2 * t4 + 3 * t3 ** 2 - 2 * t2 ** 2 * t3) * b2 * b3, t5, "A_50") if q > 5 else Fraction(0)
+    A60 = Fraction(0)
+    if q > 6:
+        num = ((5 * t2 * t5 + 3 * t3 * t4 - 2 * t2 ** 2 * t4) * b2 * b4
+               + (4 * t4 - t2 * t3) * t3 * b3 ** 2
+               + (t2 * t3 - 6 * t4) * t2 ** 2 * b2 ** 3)
+        if corrected:
+            num += 5 * t2 * t5 * b2 * A40
+        A60 = _div(num, t6, "A_60")
+    mdl.A = {4: A40, 5: A50, 6: A60}
+
+    # auxiliary moments: antiderivatives of the integrands of Sec. II
+    d1 = pderiv(Pi[1])
+    dP = {k: pderiv(Pi[k]) for k in range(2, 7)}
+    Pi0: Dict[int, Poly] = {}
+    # Pi_20 = int (Pi_1')^2
+    Pi0[2] = pinteg(ppow(d1, 2))
+    # Pi_30 = int [(Pi_1')^3 + 3 beta_2 Pi_2' Pi_1']
+    Pi0[3] = pinteg(padd(ppow(d1, 3), pscale(pmul(dP[2], d1), 3 * b2)))
+    if q > 4:
+        # eq. (Pi4): Pi_40 = int [(Pi_1')^4 + 6 beta_2 Pi_2'(Pi_1')^2 + 4 beta_3 Pi_3' Pi_1' + A_40]
+        Pi0[4] = pinteg(padd(ppow(d1, 4),
+                             pscale(pmul(dP[2], ppow(d1, 2)), 6 * b2),
+                             pscale(pmul(dP[3], d1), 4 * b3),
+                             pconst(A40)))
+    if q > 5:
+        # eq. (Pi5): Pi_50 = int [(Pi_1')^5 + 10 b2 Pi_2'(Pi_1')^3 + 10 b3 Pi_3'(Pi_1')^2 + 5 b4 Pi_4' Pi_1' + A_50]
+        terms = [ppow(d1, 5),
+                 pscale(pmul(dP[2], ppow(d1, 3)), 10 * b2),
+                 pscale(pmul(dP[3], ppow(d1, 2)), 10 * b3),
+                 pscale(pmul(dP[4], d1), 5 * b4),
+                 pconst(A50)]
+        if corrected:
+            terms.append(pscale(d1, 5 * A40))
+        Pi0[5] = pinteg(padd(*terms))
+    if q > 6:
+        # eq. (Pi6): Pi_60 = int [(Pi_1')^6 + 15 b2 Pi_2'(Pi_1')^4 + 20 b3 Pi_3'(Pi_1')^3
+        #                        + 15 b4 Pi_4'(Pi_1')^2 + 6 b5 Pi_5' Pi_1' + A_60]
+        terms = [ppow(d1, 6),
+                 pscale(pmul(dP[2], ppow(d1, 4)), 15 * b2),
+                 pscale(pmul(dP[3], ppow(d1, 3)), 20 * b3),
+                 pscale(pmul(dP[4], ppow(d1, 2)), 15 * b4),
+                 pscale(pmul(dP[5], d1), 6 * b5),
+                 pconst(A60)]
+        if corrected:
+            terms.append(pscale(ppow(d1, 2), 15 * A40))
+            terms.append(pscale(d1, 6 * A50))
+        Pi0[6] = pinteg(padd(*terms))
+    mdl.Pi0 = Pi0
+
+    # FP64 roundings (each exact value rounded once)
+    mdl.Pi_f = {k: np.array([float(c) for c in Pi[k]] or [0.0]) for k in range(1, 7)}
+    mdl.Pi0_f = {k: np.array([float(c) for c in p] or [0.0]) for k, p in Pi0.items()}
+    mdl.beta_f = {k: float(b) for k, b in beta.items()}
+    mdl.minv, mdl.minv_den = inverse_moment_matrix(q)
+    return mdl
+
+
+# ---------------------------------------------------------------------------
+# per-node quantities
+# ---------------------------------------------------------------------------
+
+def _polyval(coeffs: np.ndarray, x: np.ndarray) -> np.ndarray:
+    return np.polynomial.polynomial.polyval(x, coeffs)
+
+
+def scaled_moments(mdl: OracleModel, phi: np.ndarray) -> np.ndarray:
+    """Pi_bar_k(phi), k = 0..q-1 (Sec. III.A/B); shape (q, N)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    c = mdl.c
+    pbar = np.empty((mdl.q,) + phi.shape)
+    pbar[0] = phi
+    pbar[1] = _polyval(mdl.Pi_f[1], phi) / c
+    for k in range(2, mdl.q):
+        pbar[k] = (_polyval(mdl.Pi0_f[k], phi) + mdl.beta_f[k] * _polyval(mdl.Pi_f[k], phi)) / c ** k
+    if mdl.scheme == 2:
+        pbar[mdl.q - 1] = 0.0
+    return pbar
+
+
+def equilibrium(mdl: OracleModel, phi: np.ndarray) -> np.ndarray:
+    """f_eq = M_q^{-1} Pi_bar (Sec. III.A/B); shape (q, N)."""
+    return (mdl.minv @ scaled_moments(mdl, phi)) / mdl.minv_den
+
+
+def density(f: np.ndarray) -> np.ndarray:
+    """phi = sum_j f_j (eq. moments)."""
+    return f.sum(axis=0)
+
+
+def collide(mdl: OracleModel, f: np.ndarray) -> np.ndarray:
+    """BGK relaxation of eq. (LBE): f - (f - f_eq)/tau."""
+    feq = equilibrium(mdl, density(f))
+    return f - (f - feq) / mdl.tau
+
+
+def stream_periodic(mdl: OracleModel, fstar: np.ndarray) -> np.ndarray:
+    """f_j(x + e_j dx) = f*_j(x) on a periodic grid."""
+    out = np.empty_like(fstar)
+    for j in range(mdl.q):
+        out[j] = np.roll(fstar[j], int(mdl.e[j]))
+    return out
+
+
+def step(mdl: OracleModel, f: np.ndarray) -> np.ndarray:
+    return stream_periodic(mdl, collide(mdl, f))
+
+
+def init(mdl: OracleModel, phi0: np.ndarray) -> np.ndarray:
+    """f(x, 0) = f_eq(phi0(x))."""
+    return equilibrium(mdl, np.asarray(phi0, dtype=np.float64))
+
+
+def run(problem, phi0: np.ndarray, steps: int, mdl: Optional[OracleModel] = None,
+        return_f: bool = False):
+    """phi after `steps` collide-and-stream steps on a periodic grid."""
+    mdl = mdl or build_model(problem)
+    f = init(mdl, phi0)
+    for _ in range(int(steps)):
+        f = step(mdl, f)
+    return (density(f), f) if return_f else density(f)
+
+
+def run_f(mdl: OracleModel, f: np.ndarray, steps: int) -> np.ndarray:
+    for _ in range(int(steps)):
+        f = step(mdl, f)
+    return f
+
+
+# ---------------------------------------------------------------------------
+# bounded domains with exact-solution boundaries (paper's Sec. IV setting)
+# ---------------------------------------------------------------------------
+
+def run_bounded(problem, x: np.ndarray, exact: Callable[[np.ndarray, float], np.ndarray],
+                steps: int, kind: str, layers: Optional[int] = None,
+                report: Sequence[int] = ()) -> Dict[int, np.ndarray]:
+    """Grid x includes both end points.  After every step the `layers` outer
+    nodes on each side are reset from the exact solution at the new time:
+    kind "eq": f = f_eq(phi*); kind "nee": f = f_eq(phi*) + (f - f_eq(phi))
+    taken at the first interior node.  Returns {step: phi} for `report`."""
+    mdl = build_model(problem)
+    if layers is None:
+        layers = mdl.q // 2
+    dt = problem.dt
+    f = init(mdl, exact(x, 0.0))
+    n = x.size
+    left = np.arange(layers)
+    right = np.arange(n - layers, n)
+    out: Dict[int, np.ndarray] = {}
+    want = set(int(s) for s in report)
+    for s in range(1, int(steps) + 1):
+        f = step(mdl, f)
+        t = s * dt
+        for idx, inner in ((left, layers), (right, n - 1 - layers)):
+            phib = exact(x[idx], t)
+            feqb = equilibrium(mdl, phib)
+            if kind == "eq":
+                f[:, idx] = feqb
+            elif kind == "nee":
+                fin = f[:, inner:inner + 1]
+                neq = fin - equilibrium(mdl, density(fin))
+                f[:, idx] = feqb + neq
+            else:
+                raise ValueError(kind)
+        if s in want:
+            out[s] = density(f)
+    return out
+
+
+def global_relative_error(phi: np.ndarray, phi_exact: np.ndarray) -> float:
+    """E = sum |phi - phi*| / sum |phi*| (Sec. IV)."""
+    return float(np.sum(np.abs(phi - phi_exact)) / np.sum(np.abs(phi_exact)))
