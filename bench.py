@@ -1,0 +1,173 @@
+"""Throughput of the batched LBGK hot path on one MI355X.
+
+Workload: 4096 independent KdV / mKdV solitons (N log-uniform in [256, 4096],
+periodic, 5000 time steps each, seeded).  One bench "step" advances the whole
+batch by its 5000 lattice steps (one pass of the hot path over the batch).
+
+Reported:
+  value                 lattice-node updates per second of the batched FP32
+                        deviation path (all instances, wall clock of the timed
+                        passes, inputs resident in HBM)
+  fp64_batched          the same batch stored and computed in FP64
+  plain_fp64            one instance at a time, one fused collide+stream launch
+                        per step, FP64 (sampled instances)
+  roofline              the dominant kernel (the persistent LDS-resident batch
+                        kernel) against the VALU peak, timed with HIP events on
+                        the launch stream
+  cpu_baseline          the CPU oracle on a sample of the same instances
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from paper_0907_1720_amd import workloads as W  # noqa: E402
+
+COUNT = 4096
+LB_STEPS = 5000
+PEAK_VALU_TFLOPS = 78.6      # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 flop/FMA (FP64 = non-packed FP32)
+
+
+def algorithmic_flops_per_nu(q: int, degree: int) -> int:
+    """phi = sum_j f_j: q-1 adds; per population a degree-D Horner (D FMAs) and
+    the folded BGK update (1 FMA); an FMA counts 2 flops."""
+    return (q - 1) + 2 * q * (degree + 1)
+
+
+def _oracle_one(args):
+    i, steps = args
+    from oracle import lbm_oracle as O
+    inst = W.config2_instance(i)
+    t0 = time.perf_counter()
+    O.run(inst.problem, inst.phi0, steps)
+    return inst.problem.n * steps, time.perf_counter() - t0
+
+
+def cpu_baseline(sample: int = 32, steps: int = LB_STEPS):
+    workers = min(16, os.cpu_count() or 1, sample)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_one, [(i, steps) for i in range(sample)])
+    wall = time.perf_counter() - t0
+    nu = sum(r[0] for r in res)
+    return {"value": nu / wall, "unit": "node-updates/s", "cores": workers, "kind": "oracle",
+            "sample": f"instances 0..{sample - 1} of the 4096-instance batch, {steps} steps each, "
+                      f"numpy FP64 oracle, one process per core ({workers} processes), wall clock"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--count", type=int, default=COUNT)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the instances are independent, so several GPUs would each "
+              "run a share of the batch with no communication; multi-GPU runs are not part of this "
+              "build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0907_1720_amd import lbm
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    def build_batch(prec):
+        insts = [W.config2_instance(i, prec=prec, steps=LB_STEPS) for i in range(args.count)]
+        b = lbm.Batch([x.problem for x in insts], stream=stream.cuda_stream)
+        b.load_phi([x.phi0 for x in insts])
+        return insts, b
+
+    def run(prec):
+        insts, b = build_batch(prec)
+        nu_pass = sum(x.problem.n for x in insts) * LB_STEPS
+        flops_pass = sum(x.problem.n * LB_STEPS * algorithmic_flops_per_nu(5, 5 if x.problem.name == "kdv" else 9)
+                         for x in insts)
+        for _ in range(args.warmup):
+            b.advance(LB_STEPS)
+        torch.cuda.synchronize()
+        kern_ms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.advance(LB_STEPS)
+            kern_ms.append(b.last_advance_ms())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = [b.read_phi(i)[1] for i in (0, args.count - 1)]
+        b.close()
+        return {"nu_pass": nu_pass, "flops_pass": flops_pass, "wall_s": wall, "kernel_ms": kern_ms,
+                "nu_per_s": nu_pass * args.steps / wall, "status_ok": all(s == lbm.OK for s in st)}
+
+    r32 = run(W.F32_DEV)
+    r64 = run(W.F64)
+
+    # plain FP64 path: one instance at a time, one launch per step
+    sample = np.linspace(0, args.count - 1, args.plain_sample).astype(int)
+    nu, secs = 0, 0.0
+    for i in sample:
+        inst = W.config2_instance(int(i))
+        s = lbm.Solver(inst.problem, stream=stream.cuda_stream)
+        s.set_path(lbm.PATH_STREAM)
+        s.load_phi(inst.phi0)
+        s.advance(50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(LB_STEPS)
+        torch.cuda.synchronize()
+        secs += time.perf_counter() - t0
+        nu += inst.problem.n * LB_STEPS
+        s.close()
+    plain = nu / secs
+
+    k_ms = float(np.mean(r32["kernel_ms"]))
+    achieved = r32["flops_pass"] / (k_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                "kernel": "k_resident<5,float,double>", "kernel_ms": k_ms}
+    out = {
+        "metric": "lattice-node updates/s, batched FP32 vs plain FP64 on 1 GPU; p50/p99 latency",
+        "value": r32["nu_per_s"],
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["wall_s"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "storage": "f32 deviation from rest equilibrium",
+        "data": "synthetic",
+        "config": {"workload": f"{args.count} periodic KdV/mKdV solitons, N log-uniform [256, 4096], "
+                               f"{LB_STEPS} steps each, D1Q5, tau = 2, dt = 0.05 dx^3/delta",
+                   "instances": args.count, "lattice_steps_per_step": LB_STEPS,
+                   "node_updates_per_step": r32["nu_pass"]},
+        "fp64_batched": {"value": r64["nu_per_s"], "ms_per_step": r64["wall_s"] / args.steps * 1e3,
+                         "kernel_ms": float(np.mean(r64["kernel_ms"]))},
+        "plain_fp64": {"value": plain, "sample_instances": int(len(sample)),
+                       "path": "one fused collide+stream launch per step, one instance at a time"},
+        "speedup_vs_plain_fp64": r32["nu_per_s"] / plain,
+        "status_ok": bool(r32["status_ok"] and r64["status_ok"]),
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

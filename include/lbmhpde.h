@@ -1,0 +1,172 @@
+/*
+ * lbmhpde.h -- C ABI of the MI355X (gfx950) library for the general lattice
+ * Boltzmann (LBGK) model of Shi, He and Guo for 1D nonlinear PDEs
+ *
+ *     d_t phi + sum_{k=1..m} alpha_k d_x^k Pi_k(phi) = 0,  alpha_1 = 1, m <= 6
+ *
+ * (Sec. II.A, eq. NPDE).  One time step of the model (Sec. II.A, eq. LBE) is
+ *     phi   = sum_j f_j                                   (eq. moments)
+ *     f_eq  = M_q^{-1} Pi_bar(phi)                        (Sec. III.A/B)
+ *     f*_j  = f_j - (f_j - f_eq_j) / tau                  (eq. LBE)
+ *     f_j(x + e_j dx) = f*_j(x)                           (eq. LBE)
+ * on the D1Q5 (e = 0, 1, -1, 2, -2) or D1Q7 (e = 0, +-1, +-2, +-3) lattice,
+ * with Pi_bar_0 = phi, Pi_bar_1 = Pi_1/c, Pi_bar_k = (Pi_k0 + beta_k Pi_k)/c^k,
+ * c = dx/dt, beta_k = alpha_k / (dt^{k-1} tau_k) (eq. taus and Sec. III.C) and
+ * the auxiliary moments Pi_k0 of Sec. II.C-F.
+ *
+ * Conventions for every entry point:
+ *  - Every call returns an lbm_status; no C++ exception crosses the ABI.
+ *  - Descriptors are validated on the host before any device work; a call
+ *    that fails validation changes nothing.
+ *  - Host arrays passed in are owned by the caller and copied before return.
+ *  - A handle is not thread safe; distinct handles are independent.
+ *  - `stream` arguments are hipStream_t values (NULL = the null stream).
+ *    Work is enqueued on that stream; `*_read_*`, `*_sum_*` and `*_save_*`
+ *    synchronise it.
+ *  - State layout on the device: structure of arrays, f[j][x] with the
+ *    population index j in the paper's velocity order and row stride
+ *    lbm_row_stride(n) elements; FP64 (double) or, for the FP32 precisions,
+ *    float deviations g = f - f_rest from a per-problem rest equilibrium.
+ */
+#ifndef LBMHPDE_H
+#define LBMHPDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_INVALID_ARG = 1,   /* bad pointer, size, m/q mismatch, tau <= 1/2, degree > 4 ... */
+  LBM_ERR_UNSUPPORTED = 2,   /* a valid request this build does not implement */
+  LBM_ERR_SINGULAR_TAU = 3,  /* |tau_k| ~ 0 where beta_k or a correction A_k0 needs 1/tau_k */
+  LBM_ERR_OUT_OF_MEMORY = 4, /* device allocation failed or caller buffer too small */
+  LBM_ERR_DEVICE = 5,        /* a HIP runtime call failed */
+  LBM_ERR_NONFINITE = 6,     /* the state holds NaN or Inf (instability) */
+  LBM_ERR_BUSY = 7           /* serving: request not admitted yet / not finished */
+} lbm_status;
+
+typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_DIRICHLET_EQ = 1 } lbm_bc;
+/* LBM_F64: FP64 state and arithmetic.  LBM_F32_DEV: the state is stored in
+   FP32 as the deviation g = f - f_rest from the equilibrium of a rest state
+   phi_rest (the mean of phi0, conserved on a periodic grid); the zeroth
+   moment is summed and the relaxation evaluated in FP64.  LBM_F32_DEV_ARITH32:
+   the same storage with the relaxation polynomials evaluated in FP32 (the
+   zeroth moment still summed in FP64). */
+typedef enum { LBM_F64 = 0, LBM_F32_DEV = 1, LBM_F32_DEV_ARITH32 = 2 } lbm_precision;
+/* Auxiliary moments: LBM_AM_CORRECTED propagates the A_40 / A_50 parts of the
+   fourth and fifth moments into Pi_50, Pi_60 and A_60 (required for the O(eps^m)
+   recovery claimed in Sec. II.E-F when beta_2 != 0); LBM_AM_PAPER uses
+   eqs. (Pi5), (Pi6) and A_60 exactly as printed.  Identical when beta_2 = 0. */
+typedef enum { LBM_AM_CORRECTED = 0, LBM_AM_PAPER = 1 } lbm_am;
+
+/* Problem descriptor (Sec. II.A eq. NPDE; Sec. III).  Plain data; layout fixed. */
+typedef struct {
+  int32_t m;             /* PDE order 1..6; 0 = highest k with alpha[k] != 0 */
+  int32_t q;             /* 5 or 7; 0 = 5 if m <= 4 else 7 (Sec. III); needs q >= m + 1 */
+  int32_t scheme;        /* 1 = all q moments (default, 0 is read as 1); 2 = top moment Pi_bar_{q-1} = 0 */
+  int32_t am;            /* lbm_am */
+  double alpha[7];       /* alpha[2..6]; alpha[0], alpha[1] ignored (alpha_1 = 1) */
+  int32_t pi_deg[7];     /* Pi_k(phi) = sum_{d <= pi_deg[k]} pi_coef[k][d] phi^d, k = 1..6;
+                            -1 = absent (Pi_k = 0); degree <= 4 */
+  double pi_coef[7][5];
+  int64_t n;             /* nodes on the periodic grid, n >= q */
+  double dx, dt, tau;    /* lattice speed c = dx/dt (Sec. II.A); tau > 1/2 */
+  int32_t bc;            /* lbm_bc; only LBM_BC_PERIODIC is implemented */
+  int32_t prec;          /* lbm_precision */
+} lbm_desc;
+
+typedef struct lbm_problem_s* lbm_problem;
+typedef struct lbm_batch_s* lbm_batch;
+typedef struct lbm_server_s* lbm_server;
+
+const char* lbm_status_str(lbm_status s);
+const char* lbm_version(void);
+
+/* Elements per population row for n nodes (rows are padded for alignment). */
+int64_t lbm_row_stride(int64_t n);
+
+/* Host-only validation of a descriptor (the checks lbm_create performs). */
+lbm_status lbm_validate(const lbm_desc* d);
+
+/* Host-only: the collapsed equilibrium polynomials f_eq_j(phi) = sum_d
+   G[j*(D+1) + d] phi^d, j = 0..q-1, built once per problem in 113-bit
+   arithmetic and rounded to double (the per-node steps a2-a3:
+   Pi_k(phi) -> Pi_k0(phi) -> Pi_bar -> M_q^{-1} Pi_bar).  `cap` is the
+   capacity of G in doubles; *q_out, *degree_out receive q and D. */
+lbm_status lbm_coefficients(const lbm_desc* d, double* G, int32_t cap, int32_t* q_out,
+                            int32_t* degree_out);
+
+/* ---- single problem ---------------------------------------------------- */
+
+/* Device bytes of the state of one problem (f, one buffer; plus scratch). */
+lbm_status lbm_required_bytes(const lbm_desc* d, size_t* bytes);
+
+/* Create a problem.  dev_buf (nullable) is caller-owned device memory of at
+   least lbm_required_bytes bytes that must outlive the handle; otherwise the
+   library allocates and owns its buffers. */
+lbm_status lbm_create(const lbm_desc* d, void* stream, void* dev_buf, size_t buf_bytes,
+                      lbm_problem* out);
+
+/* f := f_eq(phi) at every node (initial distribution, Sec. IV).  phi holds n
+   doubles on the host (phi_on_device = 0) or the device (1). */
+lbm_status lbm_load_phi(lbm_problem h, const double* phi, int phi_on_device);
+
+/* Advance `steps` time steps (asynchronous on the problem's stream). */
+lbm_status lbm_advance(lbm_problem h, int64_t steps);
+
+/* phi = sum_j f_j (zeroth moment, FP64) into n doubles on the host or device.
+   Synchronises; returns LBM_ERR_NONFINITE (after writing) if any value is NaN/Inf. */
+lbm_status lbm_read_phi(lbm_problem h, double* out, int out_on_device);
+
+/* FP64 sum over the grid of phi (conserved on a periodic grid). */
+lbm_status lbm_sum_phi(lbm_problem h, double* total);
+
+/* Checkpoint / resume of the complete state (f and the step count). */
+lbm_status lbm_state_bytes(lbm_problem h, size_t* bytes);
+lbm_status lbm_save_f(lbm_problem h, void* host_buf, size_t bytes);
+lbm_status lbm_load_f(lbm_problem h, const void* host_buf, size_t bytes);
+
+/* Kernel path for lbm_advance: 0 = automatic, 1 = HBM streaming (one fused
+   collide+stream launch per step), 2 = on-chip resident (all steps of a call
+   in one launch; needs the state to fit one workgroup's LDS). */
+lbm_status lbm_set_path(lbm_problem h, int32_t path);
+
+/* Device time of the kernels of the last lbm_advance, in ms (HIP events). */
+lbm_status lbm_last_advance_ms(lbm_problem h, float* ms);
+
+lbm_status lbm_destroy(lbm_problem h);
+
+/* ---- batches of independent problems ------------------------------------ */
+
+/* `count` descriptors (any mix of q, degree, precision and n). */
+lbm_status lbm_batch_create(const lbm_desc* descs, int32_t count, void* stream, lbm_batch* out);
+
+/* phi0[i] points to descs[i].n host doubles. */
+lbm_status lbm_batch_load_phi(lbm_batch b, const double* const* phi0);
+
+/* Advance instance i by steps[i] (>= 0) steps, all instances in persistent
+   launches; asynchronous.  steps == NULL advances nothing. */
+lbm_status lbm_batch_advance(lbm_batch b, const int64_t* steps);
+
+/* phi of instance i into n host doubles; *inst_status (nullable) receives
+   LBM_OK or LBM_ERR_NONFINITE for that instance alone.  Synchronises. */
+lbm_status lbm_batch_read_phi(lbm_batch b, int32_t i, double* out, lbm_status* inst_status);
+
+/* Device time of the kernels of the last lbm_batch_advance, in ms. */
+lbm_status lbm_batch_last_advance_ms(lbm_batch b, float* ms);
+
+/* Planner: 0 = automatic, 1 = force HBM streaming for every instance,
+   2 = force on-chip resident (fails with UNSUPPORTED if an instance does not fit). */
+lbm_status lbm_batch_set_path(lbm_batch b, int32_t path);
+
+lbm_status lbm_batch_destroy(lbm_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMHPDE_H */

@@ -1,0 +1,321 @@
+// Model construction for the general LBGK model (Sec. II and Sec. III of
+// Shi, He and Guo).  See coeffs.hpp.
+//
+// Routes chosen here (the CPU test oracle takes other ones, so the two can be
+// compared):
+//  * tau_k are read off the power series of g(s) = u / (1 + tau u),
+//    u = e^s - 1, the generating function of the relaxation polynomials of
+//    eq. (taus);
+//  * the integrand of Pi_k0 is the binomial pattern common to eqs. (Pi4),
+//    (Pi5), (Pi6):  (Pi_1')^k + sum_{r=2}^{k-1} C(k,r) beta_r Pi_r' (Pi_1')^{k-r}
+//    + A_k0;
+//  * M_q^{-1} is obtained by Gauss-Jordan elimination of the moment
+//    (Vandermonde) matrix M[k][j] = e_j^k of Sec. III.A/B.
+#include "coeffs.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace lbm {
+
+const int kVelocity[kMaxQ] = {0, 1, -1, 2, -2, 3, -3};
+
+namespace {
+
+using qf = __float128;
+using QPoly = std::vector<qf>;   // ascending powers of phi
+
+QPoly trim(QPoly p) {
+  while (!p.empty() && p.back() == 0) p.pop_back();
+  return p;
+}
+
+QPoly add(const QPoly& a, const QPoly& b) {
+  QPoly r(a.size() > b.size() ? a.size() : b.size(), 0);
+  for (size_t i = 0; i < a.size(); ++i) r[i] += a[i];
+  for (size_t i = 0; i < b.size(); ++i) r[i] += b[i];
+  return trim(r);
+}
+
+QPoly scale(const QPoly& a, qf s) {
+  QPoly r(a.size());
+  for (size_t i = 0; i < a.size(); ++i) r[i] = a[i] * s;
+  return trim(r);
+}
+
+QPoly mul(const QPoly& a, const QPoly& b) {
+  if (a.empty() || b.empty()) return {};
+  QPoly r(a.size() + b.size() - 1, 0);
+  for (size_t i = 0; i < a.size(); ++i)
+    for (size_t j = 0; j < b.size(); ++j) r[i + j] += a[i] * b[j];
+  return trim(r);
+}
+
+QPoly power(const QPoly& a, int n) {
+  QPoly r{1};
+  for (int i = 0; i < n; ++i) r = mul(r, a);
+  return r;
+}
+
+QPoly deriv(const QPoly& a) {
+  QPoly r;
+  for (size_t i = 1; i < a.size(); ++i) r.push_back(a[i] * (qf)i);
+  return trim(r);
+}
+
+QPoly antideriv(const QPoly& a) {   // vanishes at phi = 0
+  QPoly r(a.size() + 1, 0);
+  for (size_t i = 0; i < a.size(); ++i) r[i + 1] = a[i] / (qf)(i + 1);
+  return trim(r);
+}
+
+qf qabs(qf x) { return x < 0 ? -x : x; }
+
+// tau_1..tau_6: coefficients of s^k in u/(1 + tau u) = sum_{r>=1} (-tau)^{r-1} u^r
+void relaxation_series(qf tau, qf out[7]) {
+  const int K = 6;
+  qf u[K + 1] = {0};
+  qf fact = 1;
+  for (int n = 1; n <= K; ++n) {
+    fact *= n;
+    u[n] = 1 / fact;
+  }
+  qf g[K + 1] = {0};
+  qf ur[K + 1] = {0};   // u^r, truncated
+  ur[0] = 1;
+  qf coef = 1;          // (-tau)^{r-1}
+  for (int r = 1; r <= K; ++r) {
+    qf next[K + 1] = {0};
+    for (int i = 0; i <= K; ++i)
+      for (int j = 1; i + j <= K; ++j) next[i + j] += ur[i] * u[j];
+    std::memcpy(ur, next, sizeof(ur));
+    for (int k = 0; k <= K; ++k) g[k] += coef * ur[k];
+    coef *= -tau;
+  }
+  for (int k = 0; k <= K; ++k) out[k] = g[k];
+}
+
+bool finite_d(double v) { return std::isfinite(v); }
+
+long long binom(int n, int k) {
+  long long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// M[k][j] = e_j^k, inverted by Gauss-Jordan with partial pivoting
+bool invert_moment_matrix(int q, qf inv[kMaxQ][kMaxQ]) {
+  qf a[kMaxQ][2 * kMaxQ];
+  for (int k = 0; k < q; ++k) {
+    for (int j = 0; j < q; ++j) {
+      qf v = 1;
+      for (int p = 0; p < k; ++p) v *= kVelocity[j];
+      a[k][j] = v;
+      a[k][q + j] = (k == j) ? 1 : 0;
+    }
+  }
+  for (int col = 0; col < q; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < q; ++r)
+      if (qabs(a[r][col]) > qabs(a[piv][col])) piv = r;
+    if (a[piv][col] == 0) return false;
+    if (piv != col)
+      for (int j = 0; j < 2 * q; ++j) {
+        qf t = a[col][j];
+        a[col][j] = a[piv][j];
+        a[piv][j] = t;
+      }
+    qf p = a[col][col];
+    for (int j = 0; j < 2 * q; ++j) a[col][j] /= p;
+    for (int r = 0; r < q; ++r) {
+      if (r == col || a[r][col] == 0) continue;
+      qf f = a[r][col];
+      for (int j = 0; j < 2 * q; ++j) a[r][j] -= f * a[col][j];
+    }
+  }
+  for (int r = 0; r < q; ++r)
+    for (int j = 0; j < q; ++j) inv[r][j] = a[r][q + j];
+  return true;
+}
+
+constexpr double kSingular = 1e-10;   // |tau_k| below this is treated as a root
+
+}  // namespace
+
+int resolved_order(const lbm_desc& d) {
+  int top = 1;
+  for (int k = 2; k <= 6; ++k)
+    if (d.alpha[k] != 0.0 && d.pi_deg[k] >= 0) top = k;
+  if (d.m == 0) return top;
+  if (d.m < 1 || d.m > 6 || d.m < top) return 0;
+  return d.m;
+}
+
+int resolved_lattice(const lbm_desc& d) {
+  int m = resolved_order(d);
+  if (m == 0) return 0;
+  if (d.q == 0) return m <= 4 ? 5 : 7;
+  if ((d.q != 5 && d.q != 7) || d.q < m + 1) return 0;
+  return d.q;
+}
+
+lbm_status build_model(const lbm_desc& d, Model* out) {
+  // ---- validation (host, before any device work) ----
+  if (!out) return LBM_ERR_INVALID_ARG;
+  if (d.scheme < 0 || d.scheme > 2 || (d.am != LBM_AM_CORRECTED && d.am != LBM_AM_PAPER))
+    return LBM_ERR_INVALID_ARG;
+  if (d.prec != LBM_F64 && d.prec != LBM_F32_DEV && d.prec != LBM_F32_DEV_ARITH32) return LBM_ERR_INVALID_ARG;
+  if (d.bc != LBM_BC_PERIODIC) return d.bc == LBM_BC_DIRICHLET_EQ ? LBM_ERR_UNSUPPORTED : LBM_ERR_INVALID_ARG;
+  for (int k = 1; k <= 6; ++k) {
+    if (d.pi_deg[k] < -1 || d.pi_deg[k] > 4) return LBM_ERR_INVALID_ARG;
+    for (int p = 0; p <= d.pi_deg[k]; ++p)
+      if (!finite_d(d.pi_coef[k][p])) return LBM_ERR_INVALID_ARG;
+    if (!finite_d(d.alpha[k])) return LBM_ERR_INVALID_ARG;
+  }
+  if (!(d.dx > 0) || !(d.dt > 0) || !finite_d(d.dx) || !finite_d(d.dt)) return LBM_ERR_INVALID_ARG;
+  if (!(d.tau > 0.5) || !finite_d(d.tau)) return LBM_ERR_INVALID_ARG;
+  const int m = resolved_order(d);
+  const int q = resolved_lattice(d);
+  if (m == 0 || q == 0) return LBM_ERR_INVALID_ARG;
+  if (d.n < q || d.n > (int64_t(1) << 30)) return LBM_ERR_INVALID_ARG;
+
+  Model mdl;
+  mdl.q = q;
+  mdl.m = m;
+  mdl.scheme = d.scheme == 2 ? 2 : 1;
+  mdl.tau = d.tau;
+  const qf dx = d.dx, dt = d.dt, tau = d.tau;
+  const qf c = dx / dt;
+  mdl.c = (double)c;
+
+  // ---- relaxation polynomials (eq. taus) ----
+  qf tk[7];
+  relaxation_series(tau, tk);
+
+  // ---- Pi_k as polynomials ----
+  QPoly Pi[7];
+  for (int k = 1; k <= 6; ++k) {
+    QPoly p;
+    for (int i = 0; i <= d.pi_deg[k]; ++i) p.push_back((qf)d.pi_coef[k][i]);
+    Pi[k] = trim(p);
+  }
+
+  // ---- beta_k = alpha_k / (dt^{k-1} tau_k), zero where alpha_k = 0 ----
+  qf beta[7] = {0};
+  for (int k = 2; k <= 6; ++k) {
+    if (k > m || d.alpha[k] == 0.0 || Pi[k].empty()) continue;
+    if (qabs(tk[k]) < kSingular) return LBM_ERR_SINGULAR_TAU;
+    qf dtp = 1;
+    for (int i = 0; i < k - 1; ++i) dtp *= dt;
+    beta[k] = (qf)d.alpha[k] / (dtp * tk[k]);
+  }
+
+  // ---- corrections A_40, A_50, A_60 ----
+  const qf t2 = tk[2], t3 = tk[3], t4 = tk[4], t5 = tk[5], t6 = tk[6];
+  const bool corrected = d.am == LBM_AM_CORRECTED;
+  qf A[7] = {0};
+  {
+    qf num = t2 * (3 * t3 - t2 * t2) * beta[2] * beta[2];
+    if (num != 0) {
+      if (qabs(t4) < kSingular) return LBM_ERR_SINGULAR_TAU;
+      A[4] = num / t4;
+    }
+  }
+  if (q > 5) {
+    qf num = (4 * t2 * t4 + 3 * t3 * t3 - 2 * t2 * t2 * t3) * beta[2] * beta[3];
+    if (num != 0) {
+      if (qabs(t5) < kSingular) return LBM_ERR_SINGULAR_TAU;
+      A[5] = num / t5;
+    }
+  }
+  if (q > 6) {
+    qf num = (5 * t2 * t5 + 3 * t3 * t4 - 2 * t2 * t2 * t4) * beta[2] * beta[4] +
+             (4 * t4 - t2 * t3) * t3 * beta[3] * beta[3] +
+             (t2 * t3 - 6 * t4) * t2 * t2 * beta[2] * beta[2] * beta[2];
+    if (corrected) num += 5 * t2 * t5 * beta[2] * A[4];
+    if (num != 0) {
+      if (qabs(t6) < kSingular) return LBM_ERR_SINGULAR_TAU;
+      A[6] = num / t6;
+    }
+  }
+
+  // ---- auxiliary moments Pi_k0 = int_0^phi I_k, k = 2..q-1 ----
+  const QPoly d1 = deriv(Pi[1]);
+  QPoly d1pow[7];
+  for (int p = 0; p <= 6; ++p) d1pow[p] = power(d1, p);
+  QPoly Pi0[7];
+  for (int k = 2; k < q; ++k) {
+    QPoly I = d1pow[k];
+    for (int r = 2; r <= k - 1; ++r) {
+      QPoly lead = scale(deriv(Pi[r]), beta[r]);
+      if (corrected && (r == 4 || r == 5)) lead = add(lead, QPoly{A[r]});
+      I = add(I, scale(mul(lead, d1pow[k - r]), (qf)binom(k, r)));
+    }
+    if (k >= 4) I = add(I, QPoly{A[k]});
+    Pi0[k] = antideriv(I);
+  }
+
+  // ---- scaled moments Pi_bar_k (Sec. III.A/B) ----
+  QPoly Pbar[kMaxQ];
+  Pbar[0] = QPoly{0, 1};
+  Pbar[1] = scale(Pi[1], 1 / c);
+  qf ck = c;
+  for (int k = 2; k < q; ++k) {
+    ck *= c;
+    Pbar[k] = scale(add(Pi0[k], scale(Pi[k], beta[k])), 1 / ck);
+  }
+  if (mdl.scheme == 2) Pbar[q - 1].clear();
+
+  // ---- collapse f_eq = M_q^{-1} Pi_bar into polynomials in phi ----
+  qf inv[kMaxQ][kMaxQ];
+  if (!invert_moment_matrix(q, inv)) return LBM_ERR_INVALID_ARG;
+  int D = 1;
+  for (int k = 0; k < q; ++k)
+    if ((int)Pbar[k].size() - 1 > D) D = (int)Pbar[k].size() - 1;
+  if (D > kMaxDeg) return LBM_ERR_UNSUPPORTED;
+  mdl.D = D;
+  const qf omega = 1 / tau;
+  mdl.w0 = (double)(1 - omega);
+  for (int j = 0; j < q; ++j) {
+    for (int p = 0; p <= D; ++p) {
+      qf g = 0;
+      for (int k = 0; k < q; ++k)
+        if (p < (int)Pbar[k].size()) g += inv[j][k] * Pbar[k][p];
+      mdl.Gq[j][p] = g;
+      mdl.G[j][p] = (double)g;
+      mdl.wG[j][p] = (double)(omega * g);
+      if (!finite_d(mdl.G[j][p]) || !finite_d(mdl.wG[j][p])) return LBM_ERR_SINGULAR_TAU;
+    }
+  }
+  set_rest_state(&mdl, 0.0);
+  *out = mdl;
+  return LBM_OK;
+}
+
+void set_rest_state(Model* mdl, double phi_rest) {
+  const qf r = phi_rest;
+  const qf omega = 1 / (qf)mdl->tau;
+  mdl->phi_rest = phi_rest;
+  for (int j = 0; j < mdl->q; ++j) {
+    // Taylor shift: f_eq_j(r + delta) = sum_p H[j][p] delta^p, H[j][p] = sum_k C(k,p) G[j][k] r^{k-p}
+    for (int p = 0; p <= mdl->D; ++p) {
+      qf h = 0;
+      qf rp = 1;
+      for (int k = p; k <= mdl->D; ++k) {
+        h += (qf)binom(k, p) * mdl->Gq[j][k] * rp;
+        rp *= r;
+      }
+      if (p == 0) {
+        mdl->f_rest[j] = (double)h;
+        mdl->H[j][0] = 0.0;
+        mdl->wH[j][0] = 0.0;
+      } else {
+        mdl->H[j][p] = (double)h;
+        mdl->wH[j][p] = (double)(omega * h);
+      }
+    }
+  }
+}
+
+}  // namespace lbm

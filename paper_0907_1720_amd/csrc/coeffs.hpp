@@ -1,0 +1,51 @@
+// Host-side model construction (once per problem): relaxation polynomials,
+// beta_k, the corrections A_k0, the auxiliary moments Pi_k0, the scaled
+// moments Pi_bar_k and their collapse through M_q^{-1} into one polynomial in
+// phi per population.  All arithmetic is 113-bit (__float128) on the exact
+// binary values of the inputs; every table entry is rounded to double once.
+#pragma once
+
+#include <cstdint>
+
+#include "lbmhpde.h"
+
+namespace lbm {
+
+constexpr int kMaxQ = 7;
+constexpr int kMaxDeg = 19;   // Pi_1 of degree 4: (Pi_1')^6 has degree 18, Pi_60 degree 19
+
+struct Model {
+  int q = 5;
+  int m = 1;
+  int D = 1;                   // degree of the equilibrium polynomials
+  int scheme = 1;
+  double tau = 1.0;
+  double c = 1.0;              // dx / dt
+  // f_eq_j(phi) = sum_d G[j][d] phi^d  (steps a2-a3 collapsed)
+  double G[kMaxQ][kMaxDeg + 1] = {};
+  // BGK with omega = 1/tau folded in: f*_j = w0 f_j + sum_d wG[j][d] phi^d
+  double wG[kMaxQ][kMaxDeg + 1] = {};
+  double w0 = 0.0;
+  // FP32 deviation storage about the rest state phi_rest:
+  // f_eq_j(phi_rest + delta) - f_rest_j = sum_{d >= 1} H[j][d] delta^d
+  double phi_rest = 0.0;
+  double f_rest[kMaxQ] = {};
+  double H[kMaxQ][kMaxDeg + 1] = {};
+  double wH[kMaxQ][kMaxDeg + 1] = {};
+  // the 113-bit table, kept for the rest-state shift
+  __float128 Gq[kMaxQ][kMaxDeg + 1] = {};
+};
+
+// Validates the descriptor and builds the model; changes nothing on failure.
+lbm_status build_model(const lbm_desc& d, Model* out);
+
+// Fills phi_rest, f_rest, H and wH for the rest state phi_rest.
+void set_rest_state(Model* mdl, double phi_rest);
+
+// Resolved order m and lattice size q of a descriptor (0 on invalid input).
+int resolved_order(const lbm_desc& d);
+int resolved_lattice(const lbm_desc& d);
+
+extern const int kVelocity[kMaxQ];
+
+}  // namespace lbm

@@ -1,0 +1,306 @@
+// HIP kernels for gfx950 (MI355X): the per-node LBGK time step of Shi, He and
+// Guo (Sec. II.A eq. LBE with the equilibria of Sec. III) and its read-outs.
+//
+//  k_init      f := f_eq(phi)                        (initial distribution)
+//  k_stream    one fused collide+stream step, state in HBM, SoA rows,
+//              coalesced loads, shifted stores with periodic wrap
+//  k_resident  persistent work-queue kernel: one workgroup per instance keeps
+//              f in LDS for all steps of the launch; streaming in place with
+//              the alternating (AA) access pattern, one barrier per step
+//  k_phi       phi = sum_j f_j  (FP64)
+//  k_sum       FP64 sum of phi over a grid, deterministic two-pass
+#include "kernels.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// f := f_eq(phi)
+// ---------------------------------------------------------------------------
+template <int Q, int D, typename T>
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi, T* __restrict__ f,
+                                              int n, int stride, const DevCoef* __restrict__ cf) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+  const double p = phi[x] - cf->phi_rest;   // phi_rest = 0 for FP64 storage
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    double acc = cf->G[j][D];
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d) acc = __builtin_fma(acc, p, cf->G[j][d]);
+    f[(int64_t)j * stride + x] = (T)acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one fused collide + stream step in HBM (push: coalesced loads, stores shifted
+// by e_j with periodic wrap)
+// ---------------------------------------------------------------------------
+template <int Q, int D, typename T, typename A>
+__global__ __launch_bounds__(256) void k_stream(const T* __restrict__ fin, T* __restrict__ fout, int n,
+                                                int stride, const DevCoef* __restrict__ cf) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+  T f[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) f[j] = fin[(int64_t)j * stride + x];
+  collide<Q, D, T, A>(f, CoefView<A>::relax(cf), CoefView<A>::w0(cf));
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    int y = x + velocity(j);
+    y += (y < 0) ? n : 0;
+    y -= (y >= n) ? n : 0;
+    fout[(int64_t)j * stride + y] = f[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-resident steps of one instance (AA pattern).
+//   even step: node x reads S[j][x], writes f*_j to S[opp(j)][x]
+//   odd step:  node x reads S[opp(j)][x - e_j], writes f*_j to S[j][x + e_j]
+// Each node reads exactly the slots it writes, so one barrier per step
+// suffices.  After an even number of steps S is in natural layout
+// (S[j][x] = f_j(x)); after an odd number f_j(x) = S[opp(j)][x - e_j].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrapn(int y, int n) {
+  y += (y < 0) ? n : 0;
+  y -= (y >= n) ? n : 0;
+  return y;
+}
+
+template <int Q, int D, typename T, typename A>
+__device__ void resident_instance(T* __restrict__ S, T* __restrict__ g, int n, int stride, int steps,
+                                  const DevCoef* __restrict__ cf, int* __restrict__ status) {
+  const int B = blockDim.x;
+  const int t = threadIdx.x;
+  const A* __restrict__ wg = CoefView<A>::relax(cf);
+  const A w0 = CoefView<A>::w0(cf);
+  constexpr int H = Q / 2;   // largest |e_j|
+
+  for (int j = 0; j < Q; ++j)
+    for (int x = t; x < n; x += B) S[j * n + x] = g[(int64_t)j * stride + x];
+  __syncthreads();
+
+  for (int s = 0; s < steps; ++s) {
+    if ((s & 1) == 0) {
+      for (int x = t; x < n; x += B) {
+        T f[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) f[j] = S[j * n + x];
+        collide<Q, D, T, A>(f, wg, w0);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) S[opposite(j) * n + x] = f[j];
+      }
+    } else {
+      for (int x = t; x < n; x += B) {
+        T f[Q];
+        if (x >= H && x < n - H) {
+#pragma unroll
+          for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * n + x - velocity(j)];
+          collide<Q, D, T, A>(f, wg, w0);
+#pragma unroll
+          for (int j = 0; j < Q; ++j) S[j * n + x + velocity(j)] = f[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * n + wrapn(x - velocity(j), n)];
+          collide<Q, D, T, A>(f, wg, w0);
+#pragma unroll
+          for (int j = 0; j < Q; ++j) S[j * n + wrapn(x + velocity(j), n)] = f[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // back to HBM in natural layout; flag non-finite values
+  bool bad = false;
+  const bool odd = (steps & 1) != 0;
+  for (int j = 0; j < Q; ++j) {
+    for (int x = t; x < n; x += B) {
+      const T v = odd ? S[opposite(j) * n + wrapn(x - velocity(j), n)] : S[j * n + x];
+      bad |= !__builtin_isfinite(v);
+      g[(int64_t)j * stride + x] = v;
+    }
+  }
+  if (bad) atomicOr(status, 1);
+  __syncthreads();
+}
+
+// Persistent kernel: workgroups take instances from a queue (sorted by work,
+// largest first) until it is empty.  Every instance runs all of its steps of
+// this launch inside LDS.  The kernel uses no static LDS, so an instance may
+// fill all 160 KiB: the queue slot is handed to the workgroup through a
+// per-workgroup word in global memory.
+template <int Q, typename T, typename A>
+__global__ __launch_bounds__(256) void k_resident(const DevInst* __restrict__ items, int count,
+                                                  int* __restrict__ counter, int* __restrict__ slots,
+                                                  T* __restrict__ state, const DevCoef* __restrict__ coefs,
+                                                  int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* L = reinterpret_cast<T*>(smem_raw);
+  int* slot = slots + blockIdx.x;
+  for (;;) {
+    if (threadIdx.x == 0)
+      __hip_atomic_store(slot, atomicAdd(counter, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    __syncthreads();
+    if (item >= count) break;
+    const DevInst it = items[item];
+    T* g = state + it.off;
+    const DevCoef* cf = coefs + it.inst;
+    int* st = status + it.inst;
+    switch (it.degree) {
+#define LBM_CASE(DD) \
+  case DD:           \
+    resident_instance<Q, DD, T, A>(L, g, it.n, it.stride, it.steps, cf, st); \
+    break;
+      LBM_DEGREE_CASES(Q)
+#undef LBM_CASE
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// read-outs
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_phi(const T* __restrict__ f, double* __restrict__ phi, int n,
+                                             int stride, int q, double phi_rest,
+                                             int* __restrict__ nonfinite) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= n) return;
+  double s = (double)f[x];
+  for (int j = 1; j < q; ++j) s += (double)f[(int64_t)j * stride + x];
+  s += phi_rest;
+  phi[x] = s;
+  if (!__builtin_isfinite(s)) atomicOr(nonfinite, 1);
+}
+
+__global__ __launch_bounds__(256) void k_sum_partial(const double* __restrict__ v, int n,
+                                                     double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) s += v[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers; `prec` selects (storage, arithmetic): 0 (double, double),
+// 1 (float, double), 2 (float, float)
+// ---------------------------------------------------------------------------
+namespace {
+template <int Q, typename T>
+hipError_t launch_init_q(int D, const double* phi, T* f, int n, int stride, const DevCoef* cf,
+                         hipStream_t s) {
+  dim3 grid((n + 255) / 256);
+  switch (D) {
+#define LBM_CASE(DD) \
+  case DD:           \
+    k_init<Q, DD, T><<<grid, 256, 0, s>>>(phi, f, n, stride, cf); \
+    return hipGetLastError();
+    LBM_DEGREE_CASES(Q)
+#undef LBM_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int Q, typename T, typename A>
+hipError_t launch_stream_q(int D, const T* fin, T* fout, int n, int stride, const DevCoef* cf,
+                           hipStream_t s) {
+  dim3 grid((n + 255) / 256);
+  switch (D) {
+#define LBM_CASE(DD) \
+  case DD:           \
+    k_stream<Q, DD, T, A><<<grid, 256, 0, s>>>(fin, fout, n, stride, cf); \
+    return hipGetLastError();
+    LBM_DEGREE_CASES(Q)
+#undef LBM_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int Q, typename T, typename A>
+const void* resident_fn() { return (const void*)k_resident<Q, T, A>; }
+
+const void* resident_kernel(int q, int prec) {
+  if (q == 5) {
+    if (prec == 0) return resident_fn<5, double, double>();
+    if (prec == 1) return resident_fn<5, float, double>();
+    return resident_fn<5, float, float>();
+  }
+  if (prec == 0) return resident_fn<7, double, double>();
+  if (prec == 1) return resident_fn<7, float, double>();
+  return resident_fn<7, float, float>();
+}
+}  // namespace
+
+hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n, int stride,
+                       const DevCoef* cf, hipStream_t s) {
+  if (prec == 0)
+    return q == 5 ? launch_init_q<5, double>(D, phi, (double*)f, n, stride, cf, s)
+                  : launch_init_q<7, double>(D, phi, (double*)f, n, stride, cf, s);
+  return q == 5 ? launch_init_q<5, float>(D, phi, (float*)f, n, stride, cf, s)
+                : launch_init_q<7, float>(D, phi, (float*)f, n, stride, cf, s);
+}
+
+hipError_t launch_stream(int q, int D, int prec, const void* fin, void* fout, int n, int stride,
+                         const DevCoef* cf, hipStream_t s) {
+  if (prec == 0)
+    return q == 5 ? launch_stream_q<5, double, double>(D, (const double*)fin, (double*)fout, n, stride, cf, s)
+                  : launch_stream_q<7, double, double>(D, (const double*)fin, (double*)fout, n, stride, cf, s);
+  if (prec == 1)
+    return q == 5 ? launch_stream_q<5, float, double>(D, (const float*)fin, (float*)fout, n, stride, cf, s)
+                  : launch_stream_q<7, float, double>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
+  return q == 5 ? launch_stream_q<5, float, float>(D, (const float*)fin, (float*)fout, n, stride, cf, s)
+                : launch_stream_q<7, float, float>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
+}
+
+hipError_t launch_resident(int q, int prec, const DevInst* items, int count, int* counter, int* slots,
+                           void* state, const DevCoef* coefs, int* status, int grid, int block, size_t lds,
+                           hipStream_t s) {
+  const void* fn = resident_kernel(q, prec);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)&items, (void*)&count, (void*)&counter, (void*)&slots, (void*)&state, (void*)&coefs,
+                  (void*)&status};
+  return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, s);
+}
+
+size_t resident_static_lds(int q, int prec) {
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, resident_kernel(q, prec)) != hipSuccess) return 1024;
+  return a.sharedSizeBytes;
+}
+
+hipError_t resident_occupancy(int q, int prec, int block, size_t lds, int* blocks_per_cu) {
+  const void* fn = resident_kernel(q, prec);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, lds);
+}
+
+hipError_t launch_phi(int prec, const void* f, double* phi, int n, int stride, int q, double phi_rest,
+                      int* nonfinite, hipStream_t s) {
+  if (prec == 0)
+    k_phi<double><<<(n + 255) / 256, 256, 0, s>>>((const double*)f, phi, n, stride, q, phi_rest, nonfinite);
+  else
+    k_phi<float><<<(n + 255) / 256, 256, 0, s>>>((const float*)f, phi, n, stride, q, phi_rest, nonfinite);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* v, int n, double* part, int nparts, hipStream_t s) {
+  k_sum_partial<<<nparts, 256, 0, s>>>(v, n, part);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

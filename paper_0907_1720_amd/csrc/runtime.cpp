@@ -1,0 +1,652 @@
+// C-ABI runtime: problem and batch handles, device memory, the planner that
+// chooses between the on-chip resident and the HBM streaming kernels, and the
+// read-outs.  Host code only; kernels live in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "coeffs.hpp"
+#include "kernels.hpp"
+#include "lbmhpde.h"
+
+using namespace lbm;
+
+#define LBM_HIP(call)                                \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return LBM_ERR_DEVICE;     \
+  } while (0)
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxResidentGrid = 256 * 8;
+constexpr uint64_t kMagic = 0x4c424d4850444531ull;   // "LBMHPDE1"
+
+struct HostInst {
+  lbm_desc desc;
+  Model mdl;
+  int q = 5;
+  int D = 5;        // padded kernel degree
+  int n = 0;
+  int stride = 0;
+  bool f32 = false;  // FP32 deviation storage
+  int prec = 0;      // lbm_precision
+  int64_t off = 0;  // element offset in its precision's state arrays
+  int cur = 0;      // which of the two state buffers is current
+  int64_t steps_done = 0;
+};
+
+struct DeviceLimits {
+  int cus = 0;
+  size_t lds_max = 0;
+  bool ok = false;
+};
+
+DeviceLimits query_limits() {
+  DeviceLimits L;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return L;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return L;
+  L.cus = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return L;
+  L.lds_max = (size_t)v;
+  L.ok = true;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_batch_s {
+  hipStream_t stream = nullptr;
+  std::vector<HostInst> inst;
+  DeviceLimits lim;
+  int path = 0;
+  // state: two buffers per precision (current / other for the streaming path)
+  double* f64[2] = {nullptr, nullptr};
+  float* f32[2] = {nullptr, nullptr};
+  size_t n64 = 0, n32 = 0;            // elements per buffer
+  bool own_state = true;
+  DevCoef* coefs = nullptr;
+  int* status = nullptr;              // per instance: 1 = non-finite seen
+  int* counter = nullptr;             // work queue counters (one per group launch)
+  int* slots = nullptr;               // per-workgroup queue slot of the resident kernel
+  int counters_cap = 0;
+  DevInst* items = nullptr;           // two slots of items_cap records (alternating calls)
+  DevInst* items_host = nullptr;      // pinned mirror of both slots
+  hipEvent_t items_done[2] = {nullptr, nullptr};
+  int items_cap = 0;
+  int slot = 0;
+  double* scratch = nullptr;          // phi read-out (max n) + partial sums
+  size_t scratch_elems = 0;
+  int* flag = nullptr;                // non-finite flag for read-outs
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  float last_ms = 0.0f;
+  std::vector<DevCoef> hcoef;
+};
+
+struct lbm_problem_s {
+  lbm_batch_s* b = nullptr;
+};
+
+namespace {
+
+void fill_devcoef(const HostInst& h, DevCoef* c) {
+  std::memset(c, 0, sizeof(*c));
+  const Model& m = h.mdl;
+  c->w0 = m.w0;
+  c->w0f = (float)m.w0;
+  if (h.f32) {
+    c->phi_rest = m.phi_rest;
+    for (int j = 0; j < m.q; ++j) {
+      c->f_rest[j] = m.f_rest[j];
+      for (int d = 0; d <= m.D; ++d) {
+        c->wG[j][d] = m.wH[j][d];
+        c->G[j][d] = m.H[j][d];
+        c->wHf[j][d] = (float)m.wH[j][d];
+      }
+    }
+  } else {
+    for (int j = 0; j < m.q; ++j)
+      for (int d = 0; d <= m.D; ++d) {
+        c->wG[j][d] = m.wG[j][d];
+        c->G[j][d] = m.G[j][d];
+      }
+  }
+}
+
+lbm_status upload_coef(lbm_batch_s* b, int i) {
+  fill_devcoef(b->inst[i], &b->hcoef[i]);
+  LBM_HIP(hipMemcpyAsync(b->coefs + i, &b->hcoef[i], sizeof(DevCoef), hipMemcpyHostToDevice, b->stream));
+  return LBM_OK;
+}
+
+size_t elem_size(const HostInst& h) { return h.f32 ? sizeof(float) : sizeof(double); }
+
+void destroy_batch(lbm_batch_s* b) {
+  if (!b) return;
+  hipStreamSynchronize(b->stream);
+  if (b->own_state) {
+    hipFree(b->f64[0]);
+    hipFree(b->f32[0]);
+  }
+  hipFree(b->f64[1]);
+  hipFree(b->f32[1]);
+  hipFree(b->coefs);
+  hipFree(b->status);
+  hipFree(b->counter);
+  hipFree(b->slots);
+  hipFree(b->items);
+  if (b->items_host) hipHostFree(b->items_host);
+  for (int k = 0; k < 2; ++k)
+    if (b->items_done[k]) hipEventDestroy(b->items_done[k]);
+  hipFree(b->scratch);
+  hipFree(b->flag);
+  if (b->ev0) hipEventDestroy(b->ev0);
+  if (b->ev1) hipEventDestroy(b->ev1);
+  delete b;
+}
+
+lbm_status prepare_instances(const lbm_desc* descs, int count, std::vector<HostInst>* out) {
+  out->resize(count);
+  for (int i = 0; i < count; ++i) {
+    HostInst& h = (*out)[i];
+    h.desc = descs[i];
+    lbm_status s = build_model(descs[i], &h.mdl);
+    if (s != LBM_OK) return s;
+    h.q = h.mdl.q;
+    h.D = padded_degree(h.mdl.D);
+    if (h.D == 0) return LBM_ERR_UNSUPPORTED;
+    h.n = (int)descs[i].n;
+    h.stride = (int)lbm_row_stride(descs[i].n);
+    h.prec = descs[i].prec;
+    h.f32 = h.prec != LBM_F64;
+  }
+  return LBM_OK;
+}
+
+lbm_status alloc_batch(lbm_batch_s* b, void* dev_buf, size_t buf_bytes) {
+  size_t n64 = 0, n32 = 0, maxn = 0;
+  for (HostInst& h : b->inst) {
+    size_t e = (size_t)h.q * h.stride;
+    if (h.f32) {
+      h.off = (int64_t)n32;
+      n32 += e;
+    } else {
+      h.off = (int64_t)n64;
+      n64 += e;
+    }
+    maxn = std::max(maxn, (size_t)h.n);
+  }
+  b->n64 = n64;
+  b->n32 = n32;
+  if (dev_buf) {
+    // caller-owned memory holds the current state buffer of the single problem
+    size_t need = n64 * sizeof(double) + n32 * sizeof(float);
+    if (buf_bytes < need) return LBM_ERR_OUT_OF_MEMORY;
+    b->own_state = false;
+    if (n64) b->f64[0] = (double*)dev_buf;
+    if (n32) b->f32[0] = (float*)dev_buf;
+  } else {
+    if (n64 && hipMalloc(&b->f64[0], n64 * sizeof(double)) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+    if (n32 && hipMalloc(&b->f32[0], n32 * sizeof(float)) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  }
+  const int count = (int)b->inst.size();
+  if (hipMalloc(&b->coefs, sizeof(DevCoef) * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  if (hipMalloc(&b->status, sizeof(int) * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  b->counters_cap = 16;   // 2 slots x up to 8 group launches
+  if (hipMalloc(&b->counter, sizeof(int) * b->counters_cap) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  // one queue slot per workgroup of a resident launch: grid <= CUs x 8 per launch, 2 x 8 launches in flight
+  if (hipMalloc(&b->slots, sizeof(int) * kMaxResidentGrid * 16) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  b->items_cap = count;
+  if (hipMalloc(&b->items, sizeof(DevInst) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  if (hipHostMalloc((void**)&b->items_host, sizeof(DevInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
+    return LBM_ERR_OUT_OF_MEMORY;
+  for (int k = 0; k < 2; ++k) LBM_HIP(hipEventCreateWithFlags(&b->items_done[k], hipEventDisableTiming));
+  b->scratch_elems = maxn + 64;
+  if (hipMalloc(&b->scratch, sizeof(double) * b->scratch_elems) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  if (hipMalloc(&b->flag, sizeof(int)) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  LBM_HIP(hipMemsetAsync(b->status, 0, sizeof(int) * count, b->stream));
+  LBM_HIP(hipEventCreate(&b->ev0));
+  LBM_HIP(hipEventCreate(&b->ev1));
+  b->hcoef.resize(count);
+  for (int i = 0; i < count; ++i) {
+    lbm_status s = upload_coef(b, i);
+    if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
+}
+
+lbm_status create_batch(const lbm_desc* descs, int count, void* stream, void* dev_buf, size_t buf_bytes,
+                        lbm_batch_s** out) {
+  if (!descs || count <= 0 || !out) return LBM_ERR_INVALID_ARG;
+  std::vector<HostInst> inst;
+  lbm_status s = prepare_instances(descs, count, &inst);
+  if (s != LBM_OK) return s;
+  lbm_batch_s* b = new (std::nothrow) lbm_batch_s();
+  if (!b) return LBM_ERR_OUT_OF_MEMORY;
+  b->stream = (hipStream_t)stream;
+  b->inst = std::move(inst);
+  b->lim = query_limits();
+  if (!b->lim.ok) {
+    delete b;
+    return LBM_ERR_DEVICE;
+  }
+  s = alloc_batch(b, dev_buf, buf_bytes);
+  if (s != LBM_OK) {
+    destroy_batch(b);
+    return s;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+double* f64_cur(lbm_batch_s* b, const HostInst& h) { return b->f64[h.cur] + h.off; }
+float* f32_cur(lbm_batch_s* b, const HostInst& h) { return b->f32[h.cur] + h.off; }
+void* state_cur(lbm_batch_s* b, const HostInst& h) {
+  return h.f32 ? (void*)f32_cur(b, h) : (void*)f64_cur(b, h);
+}
+void* state_other(lbm_batch_s* b, const HostInst& h) {
+  return h.f32 ? (void*)(b->f32[1 - h.cur] + h.off) : (void*)(b->f64[1 - h.cur] + h.off);
+}
+
+lbm_status ensure_second_buffer(lbm_batch_s* b, bool f32) {
+  if (f32) {
+    if (!b->f32[1] && b->n32 && hipMalloc(&b->f32[1], b->n32 * sizeof(float)) != hipSuccess)
+      return LBM_ERR_OUT_OF_MEMORY;
+  } else {
+    if (!b->f64[1] && b->n64 && hipMalloc(&b->f64[1], b->n64 * sizeof(double)) != hipSuccess)
+      return LBM_ERR_OUT_OF_MEMORY;
+  }
+  return LBM_OK;
+}
+
+lbm_status load_phi_one(lbm_batch_s* b, int i, const double* phi, int on_device) {
+  HostInst& h = b->inst[i];
+  std::vector<double> host;
+  if (on_device) {
+    host.resize(h.n);
+    LBM_HIP(hipMemcpyAsync(host.data(), phi, sizeof(double) * h.n, hipMemcpyDeviceToHost, b->stream));
+    LBM_HIP(hipStreamSynchronize(b->stream));
+  } else {
+    host.assign(phi, phi + h.n);
+  }
+  for (double v : host)
+    if (!std::isfinite(v)) return LBM_ERR_INVALID_ARG;
+  if (h.f32) {
+    // rest state: the mean of phi0 (conserved on a periodic grid)
+    long double s = 0;
+    for (double v : host) s += v;
+    set_rest_state(&h.mdl, (double)(s / h.n));
+  }
+  lbm_status st = upload_coef(b, i);
+  if (st != LBM_OK) return st;
+  LBM_HIP(hipMemcpyAsync(b->scratch, host.data(), sizeof(double) * h.n, hipMemcpyHostToDevice, b->stream));
+  h.cur = 0;
+  h.steps_done = 0;
+  LBM_HIP(hipMemsetAsync(b->status + i, 0, sizeof(int), b->stream));
+  LBM_HIP(launch_init(h.q, h.D, h.prec, b->scratch, state_cur(b, h), h.n, h.stride, b->coefs + i, b->stream));
+  // the scratch buffer is reused by the next call on this stream; keep order
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+bool fits_resident(const lbm_batch_s* b, const HostInst& h) {
+  return (size_t)h.q * h.n * elem_size(h) + resident_static_lds(h.q, h.prec) <= b->lim.lds_max;
+}
+
+constexpr int64_t kMaxStepsPerLaunch = int64_t(1) << 30;
+
+// One pass: every instance advances by steps[i] <= kMaxStepsPerLaunch.
+lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
+  const int count = (int)b->inst.size();
+  // resident groups by (q, precision); the rest streams through HBM
+  std::vector<int> res[2][3];   // [q == 7][prec]
+  std::vector<int> str;
+  for (int i = 0; i < count; ++i) {
+    if (steps[i] == 0) continue;
+    const HostInst& h = b->inst[i];
+    bool resident = fits_resident(b, h);
+    if (b->path == 1) resident = false;
+    if (b->path == 2 && !resident) return LBM_ERR_UNSUPPORTED;
+    if (resident)
+      res[h.q == 7][h.prec].push_back(i);
+    else
+      str.push_back(i);
+  }
+  // item records of this call go to slot `k`; wait until the copy issued from
+  // the same slot two calls ago has been consumed
+  const int k = b->slot;
+  b->slot ^= 1;
+  LBM_HIP(hipEventSynchronize(b->items_done[k]));
+  DevInst* hitems = b->items_host + (size_t)k * b->items_cap;
+  struct Launch { int q; int prec; int first, count; size_t lds; };
+  std::vector<Launch> launches;
+  int used = 0;
+  for (int qq = 0; qq < 2; ++qq) {
+    for (int pr = 0; pr < 3; ++pr) {
+      const std::vector<int>& g = res[qq][pr];
+      if (g.empty()) continue;
+      Launch L{qq ? 7 : 5, pr, used, 0, 0};
+      for (int i : g) {
+        const HostInst& h = b->inst[i];
+        DevInst& it = hitems[used++];
+        it.off = h.off;
+        it.n = h.n;
+        it.stride = h.stride;
+        it.steps = (int)steps[i];
+        it.degree = h.D;
+        it.q = h.q;
+        it.inst = i;
+        L.lds = std::max(L.lds, (size_t)h.q * h.n * elem_size(h));
+      }
+      L.count = used - L.first;
+      // largest work first (longest-processing-time order for the queue)
+      std::stable_sort(hitems + L.first, hitems + used, [](const DevInst& a, const DevInst& c) {
+        return (int64_t)a.n * a.steps > (int64_t)c.n * c.steps;
+      });
+      launches.push_back(L);
+    }
+  }
+  LBM_HIP(hipEventRecord(b->ev0, b->stream));
+  if (used) {
+    DevInst* ditems = b->items + (size_t)k * b->items_cap;
+    int* counters = b->counter + k * 8;
+    LBM_HIP(hipMemcpyAsync(ditems, hitems, sizeof(DevInst) * used, hipMemcpyHostToDevice, b->stream));
+    LBM_HIP(hipMemsetAsync(counters, 0, sizeof(int) * 8, b->stream));
+    for (size_t l = 0; l < launches.size(); ++l) {
+      const Launch& L = launches[l];
+      int per_cu = 0;
+      LBM_HIP(resident_occupancy(L.q, L.prec, kBlock, L.lds, &per_cu));
+      if (per_cu < 1) return LBM_ERR_UNSUPPORTED;
+      const int grid = std::min<int>(std::min<int>(L.count, per_cu * b->lim.cus), kMaxResidentGrid);
+      void* base = L.prec ? (void*)b->f32[0] : (void*)b->f64[0];
+      int* slots = b->slots + (size_t)(k * 8 + l) * kMaxResidentGrid;
+      LBM_HIP(launch_resident(L.q, L.prec, ditems + L.first, L.count, counters + l, slots, base, b->coefs,
+                              b->status, grid, kBlock, L.lds, b->stream));
+    }
+  }
+  LBM_HIP(hipEventRecord(b->items_done[k], b->stream));
+  // streaming instances: one fused collide+stream launch per step
+  for (int i : str) {
+    HostInst& h = b->inst[i];
+    lbm_status s = ensure_second_buffer(b, h.f32);
+    if (s != LBM_OK) return s;
+    for (int64_t t = 0; t < steps[i]; ++t) {
+      LBM_HIP(launch_stream(h.q, h.D, h.prec, state_cur(b, h), state_other(b, h), h.n, h.stride, b->coefs + i,
+                            b->stream));
+      h.cur = 1 - h.cur;
+    }
+  }
+  LBM_HIP(hipEventRecord(b->ev1, b->stream));
+  for (int i = 0; i < count; ++i) b->inst[i].steps_done += steps[i];
+  return LBM_OK;
+}
+
+lbm_status advance(lbm_batch_s* b, const int64_t* steps) {
+  const int count = (int)b->inst.size();
+  std::vector<int64_t> left(steps, steps + count);
+  for (int64_t v : left)
+    if (v < 0) return LBM_ERR_INVALID_ARG;
+  for (;;) {
+    std::vector<int64_t> now(count);
+    bool any = false;
+    for (int i = 0; i < count; ++i) {
+      now[i] = std::min(left[i], kMaxStepsPerLaunch);
+      left[i] -= now[i];
+      any |= now[i] > 0;
+    }
+    if (!any) return LBM_OK;
+    lbm_status s = advance_pass(b, now.data());
+    if (s != LBM_OK) return s;
+  }
+}
+
+// phi of instance i into the device scratch buffer; raises b->flag on NaN/Inf
+lbm_status phi_to_scratch(lbm_batch_s* b, int i) {
+  HostInst& h = b->inst[i];
+  LBM_HIP(hipMemsetAsync(b->flag, 0, sizeof(int), b->stream));
+  LBM_HIP(launch_phi(h.prec, state_cur(b, h), b->scratch, h.n, h.stride, h.q, h.f32 ? h.mdl.phi_rest : 0.0,
+                     b->flag, b->stream));
+  return LBM_OK;
+}
+
+lbm_status read_phi(lbm_batch_s* b, int i, double* out, int on_device, lbm_status* inst_status) {
+  HostInst& h = b->inst[i];
+  lbm_status s0 = phi_to_scratch(b, i);
+  if (s0 != LBM_OK) return s0;
+  LBM_HIP(hipMemcpyAsync(out, b->scratch, sizeof(double) * h.n,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
+  int flags[2] = {0, 0};
+  LBM_HIP(hipMemcpyAsync(&flags[0], b->flag, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  LBM_HIP(hipMemcpyAsync(&flags[1], b->status + i, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  lbm_status s = (flags[0] || flags[1]) ? LBM_ERR_NONFINITE : LBM_OK;
+  if (inst_status) *inst_status = s;
+  return s;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* lbm_status_str(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_INVALID_ARG: return "invalid argument";
+    case LBM_ERR_UNSUPPORTED: return "unsupported";
+    case LBM_ERR_SINGULAR_TAU: return "singular relaxation polynomial tau_k";
+    case LBM_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case LBM_ERR_DEVICE: return "HIP runtime error";
+    case LBM_ERR_NONFINITE: return "non-finite state";
+    case LBM_ERR_BUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char* lbm_version(void) { return "lbmhpde 0.1 gfx950"; }
+
+int64_t lbm_row_stride(int64_t n) { return (n + 63) / 64 * 64; }
+
+lbm_status lbm_validate(const lbm_desc* d) {
+  if (!d) return LBM_ERR_INVALID_ARG;
+  Model m;
+  return build_model(*d, &m);
+}
+
+lbm_status lbm_coefficients(const lbm_desc* d, double* G, int32_t cap, int32_t* q_out, int32_t* degree_out) {
+  if (!d || !G || !q_out || !degree_out) return LBM_ERR_INVALID_ARG;
+  Model m;
+  lbm_status s = build_model(*d, &m);
+  if (s != LBM_OK) return s;
+  if (cap < m.q * (m.D + 1)) return LBM_ERR_INVALID_ARG;
+  for (int j = 0; j < m.q; ++j)
+    for (int p = 0; p <= m.D; ++p) G[j * (m.D + 1) + p] = m.G[j][p];
+  *q_out = m.q;
+  *degree_out = m.D;
+  return LBM_OK;
+}
+
+lbm_status lbm_required_bytes(const lbm_desc* d, size_t* bytes) {
+  if (!d || !bytes) return LBM_ERR_INVALID_ARG;
+  Model m;
+  lbm_status s = build_model(*d, &m);
+  if (s != LBM_OK) return s;
+  size_t es = d->prec == LBM_F64 ? sizeof(double) : sizeof(float);
+  *bytes = (size_t)m.q * (size_t)lbm_row_stride(d->n) * es;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_desc* d, void* stream, void* dev_buf, size_t buf_bytes, lbm_problem* out) {
+  if (!d || !out) return LBM_ERR_INVALID_ARG;
+  lbm_batch_s* b = nullptr;
+  lbm_status s = create_batch(d, 1, stream, dev_buf, buf_bytes, &b);
+  if (s != LBM_OK) return s;
+  lbm_problem_s* p = new (std::nothrow) lbm_problem_s();
+  if (!p) {
+    destroy_batch(b);
+    return LBM_ERR_OUT_OF_MEMORY;
+  }
+  p->b = b;
+  *out = p;
+  return LBM_OK;
+}
+
+lbm_status lbm_load_phi(lbm_problem h, const double* phi, int phi_on_device) {
+  if (!h || !phi) return LBM_ERR_INVALID_ARG;
+  return load_phi_one(h->b, 0, phi, phi_on_device);
+}
+
+lbm_status lbm_advance(lbm_problem h, int64_t steps) {
+  if (!h || steps < 0) return LBM_ERR_INVALID_ARG;
+  return advance(h->b, &steps);
+}
+
+lbm_status lbm_read_phi(lbm_problem h, double* out, int out_on_device) {
+  if (!h || !out) return LBM_ERR_INVALID_ARG;
+  return read_phi(h->b, 0, out, out_on_device, nullptr);
+}
+
+lbm_status lbm_sum_phi(lbm_problem h, double* total) {
+  if (!h || !total) return LBM_ERR_INVALID_ARG;
+  lbm_batch_s* b = h->b;
+  HostInst& hi = b->inst[0];
+  lbm_status s = phi_to_scratch(b, 0);
+  if (s != LBM_OK) return s;
+  // deterministic FP64 reduction: fixed partition on the device, fixed order on the host
+  const int parts = 64;
+  double* part = b->scratch + hi.n;
+  LBM_HIP(launch_sum(b->scratch, hi.n, part, parts, b->stream));
+  double hp[parts];
+  LBM_HIP(hipMemcpyAsync(hp, part, sizeof(hp), hipMemcpyDeviceToHost, b->stream));
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  double t = 0.0;
+  for (int i = 0; i < parts; ++i) t += hp[i];
+  *total = t;
+  return std::isfinite(t) ? LBM_OK : LBM_ERR_NONFINITE;
+}
+
+lbm_status lbm_state_bytes(lbm_problem h, size_t* bytes) {
+  if (!h || !bytes) return LBM_ERR_INVALID_ARG;
+  const HostInst& hi = h->b->inst[0];
+  *bytes = 32 + (size_t)hi.q * hi.n * elem_size(hi);
+  return LBM_OK;
+}
+
+lbm_status lbm_save_f(lbm_problem h, void* host_buf, size_t bytes) {
+  if (!h || !host_buf) return LBM_ERR_INVALID_ARG;
+  lbm_batch_s* b = h->b;
+  HostInst& hi = b->inst[0];
+  size_t need = 0;
+  lbm_state_bytes(h, &need);
+  if (bytes < need) return LBM_ERR_INVALID_ARG;
+  unsigned char* p = (unsigned char*)host_buf;
+  uint64_t hdr[4] = {kMagic, (uint64_t)hi.steps_done, (uint64_t)hi.q | ((uint64_t)hi.f32 << 32), (uint64_t)hi.n};
+  std::memcpy(p, hdr, 32);
+  const size_t row = (size_t)hi.n * elem_size(hi);
+  for (int j = 0; j < hi.q; ++j) {
+    const void* src = hi.f32 ? (const void*)(f32_cur(b, hi) + (size_t)j * hi.stride)
+                             : (const void*)(f64_cur(b, hi) + (size_t)j * hi.stride);
+    LBM_HIP(hipMemcpyAsync(p + 32 + j * row, src, row, hipMemcpyDeviceToHost, b->stream));
+  }
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_load_f(lbm_problem h, const void* host_buf, size_t bytes) {
+  if (!h || !host_buf) return LBM_ERR_INVALID_ARG;
+  lbm_batch_s* b = h->b;
+  HostInst& hi = b->inst[0];
+  size_t need = 0;
+  lbm_state_bytes(h, &need);
+  if (bytes < need) return LBM_ERR_INVALID_ARG;
+  const unsigned char* p = (const unsigned char*)host_buf;
+  uint64_t hdr[4];
+  std::memcpy(hdr, p, 32);
+  if (hdr[0] != kMagic || hdr[2] != ((uint64_t)hi.q | ((uint64_t)hi.f32 << 32)) || hdr[3] != (uint64_t)hi.n)
+    return LBM_ERR_INVALID_ARG;
+  const size_t row = (size_t)hi.n * elem_size(hi);
+  for (int j = 0; j < hi.q; ++j) {
+    void* dst = hi.f32 ? (void*)(f32_cur(b, hi) + (size_t)j * hi.stride)
+                       : (void*)(f64_cur(b, hi) + (size_t)j * hi.stride);
+    LBM_HIP(hipMemcpyAsync(dst, p + 32 + j * row, row, hipMemcpyHostToDevice, b->stream));
+  }
+  LBM_HIP(hipMemsetAsync(b->status, 0, sizeof(int), b->stream));
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  hi.steps_done = (int64_t)hdr[1];
+  return LBM_OK;
+}
+
+lbm_status lbm_set_path(lbm_problem h, int32_t path) {
+  if (!h || path < 0 || path > 2) return LBM_ERR_INVALID_ARG;
+  h->b->path = path;
+  return LBM_OK;
+}
+
+lbm_status lbm_last_advance_ms(lbm_problem h, float* ms) {
+  if (!h || !ms) return LBM_ERR_INVALID_ARG;
+  return lbm_batch_last_advance_ms(h->b, ms);
+}
+
+lbm_status lbm_destroy(lbm_problem h) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  destroy_batch(h->b);
+  delete h;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_create(const lbm_desc* descs, int32_t count, void* stream, lbm_batch* out) {
+  return create_batch(descs, count, stream, nullptr, 0, out);
+}
+
+lbm_status lbm_batch_load_phi(lbm_batch b, const double* const* phi0) {
+  if (!b || !phi0) return LBM_ERR_INVALID_ARG;
+  for (size_t i = 0; i < b->inst.size(); ++i)
+    if (!phi0[i]) return LBM_ERR_INVALID_ARG;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    lbm_status s = load_phi_one(b, (int)i, phi0[i], 0);
+    if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_advance(lbm_batch b, const int64_t* steps) {
+  if (!b) return LBM_ERR_INVALID_ARG;
+  if (!steps) return LBM_OK;
+  return advance(b, steps);
+}
+
+lbm_status lbm_batch_read_phi(lbm_batch b, int32_t i, double* out, lbm_status* inst_status) {
+  if (!b || !out || i < 0 || i >= (int32_t)b->inst.size()) return LBM_ERR_INVALID_ARG;
+  lbm_status s = read_phi(b, i, out, 0, inst_status);
+  return s == LBM_ERR_NONFINITE ? LBM_OK : s;
+}
+
+lbm_status lbm_batch_last_advance_ms(lbm_batch b, float* ms) {
+  if (!b || !ms) return LBM_ERR_INVALID_ARG;
+  LBM_HIP(hipEventSynchronize(b->ev1));
+  LBM_HIP(hipEventElapsedTime(ms, b->ev0, b->ev1));
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_path(lbm_batch b, int32_t path) {
+  if (!b || path < 0 || path > 2) return LBM_ERR_INVALID_ARG;
+  b->path = path;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_destroy(lbm_batch b) {
+  if (!b) return LBM_ERR_INVALID_ARG;
+  destroy_batch(b);
+  return LBM_OK;
+}
+
+}  // extern "C"

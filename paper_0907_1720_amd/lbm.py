@@ -1,0 +1,288 @@
+"""ctypes binding of liblbmhpde.so (include/lbmhpde.h).
+
+Argument marshalling only: every step of the time step runs in the HIP
+kernels of the library.  PyTorch, when present, supplies device memory and
+the current stream.  There is no CPU fallback: if the library has not been
+built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from .workloads import Problem
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmhpde.so")
+
+OK, INVALID_ARG, UNSUPPORTED, SINGULAR_TAU, OUT_OF_MEMORY, DEVICE, NONFINITE, BUSY = range(8)
+PATH_AUTO, PATH_STREAM, PATH_RESIDENT = 0, 1, 2
+
+
+class LbmDesc(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
+        ("am", ctypes.c_int32),
+        ("alpha", ctypes.c_double * 7),
+        ("pi_deg", ctypes.c_int32 * 7),
+        ("pi_coef", (ctypes.c_double * 5) * 7),
+        ("n", ctypes.c_int64),
+        ("dx", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("bc", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+    ]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -m paper_0907_1720_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    DP = ctypes.POINTER(LbmDesc)
+    sig = {
+        "lbm_status_str": (ctypes.c_char_p, [I32]),
+        "lbm_version": (ctypes.c_char_p, []),
+        "lbm_row_stride": (I64, [I64]),
+        "lbm_validate": (I32, [DP]),
+        "lbm_coefficients": (I32, [DP, P, I32, P, P]),
+        "lbm_required_bytes": (I32, [DP, P]),
+        "lbm_create": (I32, [DP, P, P, SZ, P]),
+        "lbm_load_phi": (I32, [P, P, I32]),
+        "lbm_advance": (I32, [P, I64]),
+        "lbm_read_phi": (I32, [P, P, I32]),
+        "lbm_sum_phi": (I32, [P, P]),
+        "lbm_state_bytes": (I32, [P, P]),
+        "lbm_save_f": (I32, [P, P, SZ]),
+        "lbm_load_f": (I32, [P, P, SZ]),
+        "lbm_set_path": (I32, [P, I32]),
+        "lbm_last_advance_ms": (I32, [P, P]),
+        "lbm_destroy": (I32, [P]),
+        "lbm_batch_create": (I32, [DP, I32, P, P]),
+        "lbm_batch_load_phi": (I32, [P, P]),
+        "lbm_batch_advance": (I32, [P, P]),
+        "lbm_batch_read_phi": (I32, [P, I32, P, P]),
+        "lbm_batch_last_advance_ms": (I32, [P, P]),
+        "lbm_batch_set_path": (I32, [P, I32]),
+        "lbm_batch_destroy": (I32, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_str(s: int) -> str:
+    try:
+        return library().lbm_status_str(int(s)).decode()
+    except ImportError:
+        return "status"
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise LBMError(status, what)
+
+
+def make_desc(p: Problem) -> LbmDesc:
+    d = LbmDesc()
+    d.m = int(p.m)
+    d.q = int(p.q)
+    d.scheme = int(p.scheme)
+    d.am = int(p.am)
+    for k in range(7):
+        d.alpha[k] = float(p.alpha[k]) if k < len(p.alpha) else 0.0
+        coeffs = p.pi[k] if k < len(p.pi) else ()
+        if k == 0 or len(coeffs) == 0:
+            d.pi_deg[k] = -1
+        else:
+            if len(coeffs) > 5:
+                raise ValueError("Pi_k of degree > 4")
+            d.pi_deg[k] = len(coeffs) - 1
+            for i, c in enumerate(coeffs):
+                d.pi_coef[k][i] = float(c)
+    d.n = int(p.n)
+    d.dx, d.dt, d.tau = float(p.dx), float(p.dt), float(p.tau)
+    d.bc = 0
+    d.prec = int(p.prec)
+    return d
+
+
+def validate(p: Problem) -> int:
+    return library().lbm_validate(ctypes.byref(make_desc(p)))
+
+
+def coefficients(p: Problem) -> np.ndarray:
+    """Host-built equilibrium polynomials G, shape (q, D + 1): f_eq_j = sum_d G[j, d] phi^d."""
+    buf = np.zeros(7 * 20, dtype=np.float64)
+    q, D = ctypes.c_int32(), ctypes.c_int32()
+    _check(library().lbm_coefficients(ctypes.byref(make_desc(p)), buf.ctypes.data, buf.size,
+                                      ctypes.byref(q), ctypes.byref(D)), "lbm_coefficients")
+    return buf[: q.value * (D.value + 1)].reshape(q.value, D.value + 1).copy()
+
+
+def _current_stream() -> int:
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return 0
+
+
+class Solver:
+    """One periodic problem on the GPU (lbm_create ... lbm_destroy)."""
+
+    def __init__(self, p: Problem, stream: Optional[int] = None, dev_buf=None):
+        lib = library()
+        self.problem = p
+        self._desc = make_desc(p)
+        self.stream = _current_stream() if stream is None else int(stream)
+        h = ctypes.c_void_p()
+        buf_ptr, buf_bytes = None, 0
+        if dev_buf is not None:   # e.g. a torch CUDA tensor that outlives the solver
+            buf_ptr, buf_bytes = int(dev_buf.data_ptr()), int(dev_buf.numel() * dev_buf.element_size())
+            self._keep = dev_buf
+        _check(lib.lbm_create(ctypes.byref(self._desc), self.stream, buf_ptr, buf_bytes, ctypes.byref(h)),
+               "lbm_create")
+        self._h = h
+
+    @staticmethod
+    def required_bytes(p: Problem) -> int:
+        n = ctypes.c_size_t()
+        _check(library().lbm_required_bytes(ctypes.byref(make_desc(p)), ctypes.byref(n)), "lbm_required_bytes")
+        return n.value
+
+    def load_phi(self, phi):
+        if hasattr(phi, "data_ptr") and getattr(phi, "is_cuda", False):
+            _check(library().lbm_load_phi(self._h, int(phi.data_ptr()), 1), "lbm_load_phi")
+        else:
+            a = np.ascontiguousarray(phi, dtype=np.float64)
+            assert a.size == self.problem.n
+            _check(library().lbm_load_phi(self._h, a.ctypes.data, 0), "lbm_load_phi")
+
+    def advance(self, steps: int):
+        _check(library().lbm_advance(self._h, int(steps)), "lbm_advance")
+
+    def read_phi(self, out=None, allow_nonfinite: bool = False) -> np.ndarray:
+        if out is not None and hasattr(out, "data_ptr"):
+            s = library().lbm_read_phi(self._h, int(out.data_ptr()), 1)
+            res = out
+        else:
+            res = np.empty(self.problem.n, dtype=np.float64)
+            s = library().lbm_read_phi(self._h, res.ctypes.data, 0)
+        if not (allow_nonfinite and s == NONFINITE):
+            _check(s, "lbm_read_phi")
+        return res
+
+    def sum_phi(self) -> float:
+        t = ctypes.c_double()
+        _check(library().lbm_sum_phi(self._h, ctypes.byref(t)), "lbm_sum_phi")
+        return t.value
+
+    def save(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(library().lbm_state_bytes(self._h, ctypes.byref(n)), "lbm_state_bytes")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(library().lbm_save_f(self._h, buf, n.value), "lbm_save_f")
+        return buf.raw
+
+    def load(self, blob: bytes):
+        _check(library().lbm_load_f(self._h, blob, len(blob)), "lbm_load_f")
+
+    def set_path(self, path: int):
+        _check(library().lbm_set_path(self._h, int(path)), "lbm_set_path")
+
+    def last_advance_ms(self) -> float:
+        ms = ctypes.c_float()
+        _check(library().lbm_last_advance_ms(self._h, ctypes.byref(ms)), "lbm_last_advance_ms")
+        return ms.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent problems advanced together (lbm_batch_*)."""
+
+    def __init__(self, problems: Sequence[Problem], stream: Optional[int] = None):
+        lib = library()
+        self.problems = list(problems)
+        arr = (LbmDesc * len(self.problems))(*[make_desc(p) for p in self.problems])
+        self._descs = arr
+        self.stream = _current_stream() if stream is None else int(stream)
+        h = ctypes.c_void_p()
+        _check(lib.lbm_batch_create(arr, len(self.problems), self.stream, ctypes.byref(h)), "lbm_batch_create")
+        self._h = h
+
+    def load_phi(self, phis: Sequence[np.ndarray]):
+        keep = [np.ascontiguousarray(p, dtype=np.float64) for p in phis]
+        for a, p in zip(keep, self.problems):
+            assert a.size == p.n
+        ptrs = (ctypes.c_void_p * len(keep))(*[a.ctypes.data for a in keep])
+        _check(library().lbm_batch_load_phi(self._h, ptrs), "lbm_batch_load_phi")
+
+    def advance(self, steps):
+        if np.isscalar(steps):
+            steps = [int(steps)] * len(self.problems)
+        s = np.ascontiguousarray(steps, dtype=np.int64)
+        assert s.size == len(self.problems)
+        _check(library().lbm_batch_advance(self._h, s.ctypes.data), "lbm_batch_advance")
+
+    def read_phi(self, i: int):
+        """(phi, status) of instance i; status is OK or NONFINITE for that instance."""
+        out = np.empty(self.problems[i].n, dtype=np.float64)
+        st = ctypes.c_int32()
+        _check(library().lbm_batch_read_phi(self._h, int(i), out.ctypes.data, ctypes.byref(st)),
+               "lbm_batch_read_phi")
+        return out, st.value
+
+    def set_path(self, path: int):
+        _check(library().lbm_batch_set_path(self._h, int(path)), "lbm_batch_set_path")
+
+    def last_advance_ms(self) -> float:
+        ms = ctypes.c_float()
+        _check(library().lbm_batch_last_advance_ms(self._h, ctypes.byref(ms)), "lbm_batch_last_advance_ms")
+        return ms.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

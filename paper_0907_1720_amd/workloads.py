@@ -26,7 +26,8 @@ import numpy as np
 BASE_SEED = 20261203
 
 F64 = 0
-F32_DEV = 1
+F32_DEV = 1           # FP32 deviation storage, FP64 relaxation
+F32_DEV_ARITH32 = 2   # FP32 deviation storage, FP32 relaxation
 
 
 @dataclasses.dataclass

@@ -1,0 +1,123 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load and export every entry point that include/lbmhpde.h
+declares; its host model construction (relaxation polynomials, beta_k,
+auxiliary moments, collapse through M_q^{-1}) must agree with the oracle's
+structured equilibrium; descriptor validation must reject bad input before
+any device work.
+"""
+import ctypes
+import dataclasses
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import lbm_oracle as O
+from paper_0907_1720_amd import lbm
+from paper_0907_1720_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "lbmhpde.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = lbm.library()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.lbm_version().decode().startswith("lbmhpde")
+
+
+def test_status_strings_and_stride():
+    lib = lbm.library()
+    for s in range(8):
+        assert lib.lbm_status_str(s)
+    assert lib.lbm_row_stride(1) == 64
+    assert lib.lbm_row_stride(64) == 64
+    assert lib.lbm_row_stride(65) == 128
+
+
+def _quartic_family():
+    # u_t + (a u^2/2 + b u^4/4)_x + sum alpha_k d^k u = 0 on D1Q7
+    return W.Problem((0.0, 1.0, 0.3, -0.2, 0.4, -0.1, -0.05),
+                     ((), (0.0, 0.0, 0.5, 0.0, 0.25)) + ((0.0, 1.0),) * 5, 64, 0.1, 1e-4, 1.7)
+
+
+PROBLEMS = {
+    "kdv": W.kdv(1.0, 64, 0.05, 2e-4, 5.0, 0.0),
+    "mkdv": W.mkdv(0.7, 64, 0.1, 1e-4, 2.0, 0.0),
+    "ks": W.kuramoto_sivashinsky(64, 0.1, 1e-3, 2.0, 0.0),
+    "kawahara": W.kawahara(64, 0.0586, 1.3e-5, 3.0, 0.0),
+    "kawahara_s2": dataclasses.replace(W.kawahara(64, 0.0586, 1.3e-5, 3.0, 0.0), scheme=2),
+    "k22": W.k22(64, 0.05, 1.25e-5, 2.0, 0.0),
+    "kdv_burgers": W.kdv_burgers(0.05, 1.0, 64, 0.05, 1e-4, 2.0, 0.0),
+    "random_m6": W.random_m6_problem(W.rng(99, 0), 64),
+    "random_m6_paper_am": dataclasses.replace(W.random_m6_problem(W.rng(99, 1), 64), am=1),
+    "quartic_q7": _quartic_family(),
+    "ks_on_q7": dataclasses.replace(W.kuramoto_sivashinsky(64, 0.1, 1e-3, 2.0, 0.0), q=7),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_collapsed_equilibrium_matches_oracle(name):
+    p = PROBLEMS[name]
+    G = lbm.coefficients(p)
+    mdl = O.build_model(p)
+    assert G.shape[0] == mdl.q
+    phi = np.linspace(-2.0, 3.0, 101)
+    want = O.equilibrium(mdl, phi)
+    powers = phi[None, :] ** np.arange(G.shape[1])[:, None]
+    got = G @ powers
+    scale = np.abs(G) @ np.abs(powers) + np.abs(want) + 1e-300
+    assert np.max(np.abs(got - want) / scale) < 1e-13
+
+
+def test_validation_rejects_bad_descriptors():
+    lib = lbm.library()
+    good = W.kdv(1.0, 64, 0.05, 2e-4, 5.0, 0.0)
+    assert lbm.validate(good) == lbm.OK
+    assert lbm.validate(dataclasses.replace(good, tau=0.5)) == lbm.INVALID_ARG
+    assert lbm.validate(dataclasses.replace(good, tau=float("nan"))) == lbm.INVALID_ARG
+    assert lbm.validate(dataclasses.replace(good, dt=0.0)) == lbm.INVALID_ARG
+    assert lbm.validate(dataclasses.replace(good, n=4)) == lbm.INVALID_ARG
+    assert lbm.validate(dataclasses.replace(good, q=6)) == lbm.INVALID_ARG
+    assert lbm.validate(dataclasses.replace(good, q=7)) == lbm.OK
+    assert lbm.validate(dataclasses.replace(good, m=2)) == lbm.INVALID_ARG     # alpha_3 != 0 needs m >= 3
+    assert lbm.validate(dataclasses.replace(good, scheme=3)) == lbm.INVALID_ARG
+    assert lbm.validate(dataclasses.replace(PROBLEMS["kawahara"], q=5)) == lbm.INVALID_ARG
+    d = lbm.make_desc(good)
+    d.pi_deg[1] = 5
+    assert lib.lbm_validate(ctypes.byref(d)) == lbm.INVALID_ARG
+    d = lbm.make_desc(good)
+    d.bc = 1
+    assert lib.lbm_validate(ctypes.byref(d)) == lbm.UNSUPPORTED
+    d = lbm.make_desc(good)
+    d.prec = 7
+    assert lib.lbm_validate(ctypes.byref(d)) == lbm.INVALID_ARG
+    assert lib.lbm_validate(None) == lbm.INVALID_ARG
+
+
+def test_near_root_of_relaxation_polynomial_is_singular():
+    # tau_3 = tau^2 - tau + 1/6 vanishes at (3 + sqrt 3)/6; alpha_3 != 0 needs 1/tau_3
+    tau = (3.0 + math.sqrt(3.0)) / 6.0
+    p = W.kdv(1.0, 64, 0.05, 2e-4, tau, 0.0)
+    assert lbm.validate(p) == lbm.SINGULAR_TAU
+    # the same tau is fine when alpha_3 = 0 (pure advection)
+    adv = W.Problem((0.0, 1.0, 0, 0, 0, 0, 0), ((), (0.0, 0.0, 0.5)) + ((),) * 5, 64, 0.05, 2e-4, tau)
+    assert lbm.validate(adv) == lbm.OK
+
+
+def test_required_bytes():
+    p = W.kdv(1.0, 100, 0.05, 2e-4, 5.0, 0.0)
+    assert lbm.Solver.required_bytes(p) == 5 * 128 * 8
+    p32 = dataclasses.replace(W.kawahara(100, 0.0586, 1.3e-5, 3.0, 0.0), prec=W.F32_DEV)
+    assert lbm.Solver.required_bytes(p32) == 7 * 128 * 4
