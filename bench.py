@@ -38,10 +38,18 @@ LB_STEPS = 5000
 PEAK_VALU_TFLOPS = 78.6      # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 flop/FMA (FP64 = non-packed FP32)
 
 
-def algorithmic_flops_per_nu(q: int, degree: int) -> int:
-    """phi = sum_j f_j: q-1 adds; per population a degree-D Horner (D FMAs) and
-    the folded BGK update (1 FMA); an FMA counts 2 flops."""
-    return (q - 1) + 2 * q * (degree + 1)
+def algorithmic_flops_per_nu(G: np.ndarray) -> int:
+    """Arithmetic of one node update for the equilibrium polynomials G (q x (D+1)):
+    phi = sum_j f_j (q - 1 adds); per population the polynomial by Horner over
+    its nonzero structure and the BGK update with omega folded in (1 FMA).
+    Dense: D FMAs.  Odd in phi (every nonzero degree odd, e.g. mKdV): one shared
+    phi^2, (D-1)/2 FMAs in phi^2 and one multiply by phi.  An FMA is 2 flops."""
+    q, D = G.shape[0], G.shape[1] - 1
+    odd = not np.any(G[:, 0::2])
+    if odd:
+        K = (D + 1) // 2
+        return (q - 1) + 1 + q * (2 * (K - 1) + 1 + 2)
+    return (q - 1) + q * (2 * D + 2)
 
 
 def _oracle_one(args):
@@ -95,8 +103,11 @@ def main():
     def run(prec):
         insts, b = build_batch(prec)
         nu_pass = sum(x.problem.n for x in insts) * LB_STEPS
-        flops_pass = sum(x.problem.n * LB_STEPS * algorithmic_flops_per_nu(5, 5 if x.problem.name == "kdv" else 9)
-                         for x in insts)
+        fpn = {}
+        for x in insts:
+            if x.problem.name not in fpn:
+                fpn[x.problem.name] = algorithmic_flops_per_nu(lbm.coefficients(x.problem))
+        flops_pass = sum(x.problem.n * LB_STEPS * fpn[x.problem.name] for x in insts)
         for _ in range(args.warmup):
             b.advance(LB_STEPS)
         torch.cuda.synchronize()

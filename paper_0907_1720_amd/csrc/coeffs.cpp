@@ -308,6 +308,7 @@ void set_rest_state(Model* mdl, double phi_rest) {
       }
       if (p == 0) {
         mdl->f_rest[j] = (double)h;
+        mdl->wfrest[j] = (double)(omega * h);
         mdl->H[j][0] = 0.0;
         mdl->wH[j][0] = 0.0;
       } else {

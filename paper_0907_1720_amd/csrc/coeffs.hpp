@@ -30,6 +30,7 @@ struct Model {
   // f_eq_j(phi_rest + delta) - f_rest_j = sum_{d >= 1} H[j][d] delta^d
   double phi_rest = 0.0;
   double f_rest[kMaxQ] = {};
+  double wfrest[kMaxQ] = {};   // omega * f_rest_j
   double H[kMaxQ][kMaxDeg + 1] = {};
   double wH[kMaxQ][kMaxDeg + 1] = {};
   // the 113-bit table, kept for the rest-state shift

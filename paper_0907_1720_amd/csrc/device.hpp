@@ -12,13 +12,14 @@ constexpr int kRow = 20;   // coefficient row length (max degree 19 + 1)
 // Per-problem constants on the device.
 struct DevCoef {
   double w0;                 // 1 - omega
-  double phi_rest;           // rest state (F32 deviation storage); 0 for FP64
-  double f_rest[8];
-  double wG[8][kRow];        // FP64: omega * G[j][d];  F32-dev: omega * H[j][d] (d >= 1)
-  double G[8][kRow];         // FP64: G[j][d];          F32-dev: H[j][d]   (for f := f_eq(phi))
+  double s0;                 // added to sum_j f_j: 0, or phi_rest for FP32 storage with FP64 relaxation
+  double phi_rest;           // rest state of the FP32 deviation storage (0 for FP64 storage)
+  double cst[8];             // added after relaxation: 0, or -omega f_rest_j (FP32 storage, FP64 relaxation)
+  double wc[8][kRow];        // FP64 relaxation: omega * G[j][d] over the kept degrees (all, or odd only)
+  double init[8][kRow];      // f := f_eq(phi): G[j][d] (FP64 storage) or H[j][d] (FP32 deviations)
   float w0f;
   float pad_[3];
-  float wHf[8][kRow];        // F32-dev: omega * H[j][d] rounded to float
+  float wHf[8][kRow];        // FP32 relaxation: omega * H[j][d], H = G shifted to the rest state
 };
 
 // Per-instance launch record of the batched kernels.
@@ -27,7 +28,7 @@ struct DevInst {
   int32_t n;                 // nodes
   int32_t stride;            // row stride in elements
   int32_t steps;             // steps to run in this launch
-  int32_t degree;            // padded degree D of the kernel variant
+  int32_t degree;            // kernel variant: padded degree D | (parity << 8)
   int32_t q;
   int32_t inst;              // index into coefficients / status
 };
@@ -42,38 +43,78 @@ __host__ __device__ constexpr int opposite(int j) {
 
 // ---- a1 + a2 + a3 + a4: phi = sum_j f_j, f_eq_j(phi) by Horner, BGK ----
 //
-// Storage type T, arithmetic type A.  The zeroth moment is always summed in
-// FP64.  With FP64 storage the polynomials are G (f_eq_j(phi) = sum_d G phi^d);
-// with FP32 deviation storage g = f - f_rest they are H, the Taylor shift of
-// G about the rest state (f_eq_j(phi_rest + delta) - f_rest_j = sum_d H delta^d,
-// H[j][0] = 0), so the same code serves both:
-//     f*_j = w0 f_j + sum_d (omega C[j][d]) s^d,   s = sum_j f_j,  w0 = 1 - omega.
+// Storage type T, arithmetic type A; the zeroth moment is always summed in
+// FP64.  Three precisions share this function:
+//  * FP64 storage:  f*_j = w0 f_j + sum_d (omega G[j][d]) phi^d
+//  * FP32 deviations g = f - f_rest, FP64 relaxation (REST):
+//        phi = phi_rest + sum_j g_j,
+//        g*_j = w0 g_j + sum_d (omega G[j][d]) phi^d - omega f_rest_j
+//  * FP32 deviations, FP32 relaxation: delta = sum_j g_j,
+//        g*_j = w0 g_j + sum_d (omega H[j][d]) delta^d  with H the Taylor shift
+//        of G to the rest state (H[j][0] = 0)
+// Parity P = 1 marks equilibria that are odd in phi (every kept degree odd,
+// e.g. mKdV): coefficient k belongs to degree 2k+1 and Horner runs in phi^2.
 __device__ __forceinline__ double fma_a(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_a(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-template <int Q, int D, typename T, typename A>
-__device__ __forceinline__ void collide(T (&f)[Q], const A* __restrict__ wc, A w0) {
+template <int D, int P, typename A>
+__device__ __forceinline__ A poly_eval(const A* __restrict__ c, A p) {
+  if constexpr (P == 0) {
+    A acc = c[D];
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d) acc = fma_a(acc, p, c[d]);
+    return acc;
+  } else {
+    constexpr int K = (D + 1) / 2;   // degrees 1, 3, ..., D
+    const A u = p * p;
+    A acc = c[K - 1];
+#pragma unroll
+    for (int k = K - 2; k >= 0; --k) acc = fma_a(acc, u, c[k]);
+    return acc * p;
+  }
+}
+
+template <int Q, int D, int P, typename T, typename A, bool REST>
+__device__ __forceinline__ void collide(T (&f)[Q], const A* __restrict__ wc, A w0, double s0,
+                                        const double* __restrict__ cst) {
   double s = (double)f[0];
+  if constexpr (REST) s = s0 + s;
 #pragma unroll
   for (int j = 1; j < Q; ++j) s += (double)f[j];
   const A p = (A)s;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    A acc = wc[j * kRow + D];
-#pragma unroll
-    for (int d = D - 1; d >= 0; --d) acc = fma_a(acc, p, wc[j * kRow + d]);
-    f[j] = (T)fma_a(w0, (A)f[j], acc);
+    const A acc = poly_eval<D, P, A>(wc + j * kRow, p);
+    if constexpr (REST)
+      f[j] = (T)(fma_a(w0, (A)f[j], acc) + cst[j]);
+    else
+      f[j] = (T)fma_a(w0, (A)f[j], acc);
   }
 }
 
-template <typename A> struct CoefView;
-template <> struct CoefView<double> {
-  __device__ static const double* relax(const DevCoef* c) { return &c->wG[0][0]; }
+// Coefficient views by (storage, arithmetic)
+template <typename T, typename A> struct Relax;
+template <> struct Relax<double, double> {
+  static constexpr bool kRest = false;
+  __device__ static const double* coef(const DevCoef* c) { return &c->wc[0][0]; }
   __device__ static double w0(const DevCoef* c) { return c->w0; }
 };
-template <> struct CoefView<float> {
-  __device__ static const float* relax(const DevCoef* c) { return &c->wHf[0][0]; }
+template <> struct Relax<float, double> {
+  static constexpr bool kRest = true;
+  __device__ static const double* coef(const DevCoef* c) { return &c->wc[0][0]; }
+  __device__ static double w0(const DevCoef* c) { return c->w0; }
+};
+template <> struct Relax<float, float> {
+  static constexpr bool kRest = false;
+  __device__ static const float* coef(const DevCoef* c) { return &c->wHf[0][0]; }
   __device__ static float w0(const DevCoef* c) { return c->w0f; }
 };
+
+// one node update, the form every kernel calls
+template <int Q, int D, int P, typename T, typename A>
+__device__ __forceinline__ void collide_node(T (&f)[Q], const A* __restrict__ wc, A w0,
+                                             const DevCoef* __restrict__ cf) {
+  collide<Q, D, P, T, A, Relax<T, A>::kRest>(f, wc, w0, cf->s0, cf->cst);
+}
 
 }  // namespace lbm

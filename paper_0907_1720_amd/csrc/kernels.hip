@@ -23,19 +23,14 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi, T*
   if (x >= n) return;
   const double p = phi[x] - cf->phi_rest;   // phi_rest = 0 for FP64 storage
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    double acc = cf->G[j][D];
-#pragma unroll
-    for (int d = D - 1; d >= 0; --d) acc = __builtin_fma(acc, p, cf->G[j][d]);
-    f[(int64_t)j * stride + x] = (T)acc;
-  }
+  for (int j = 0; j < Q; ++j) f[(int64_t)j * stride + x] = (T)poly_eval<D, 0, double>(cf->init[j], p);
 }
 
 // ---------------------------------------------------------------------------
 // one fused collide + stream step in HBM (push: coalesced loads, stores shifted
 // by e_j with periodic wrap)
 // ---------------------------------------------------------------------------
-template <int Q, int D, typename T, typename A>
+template <int Q, int D, int P, typename T, typename A>
 __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ fin, T* __restrict__ fout, int n,
                                                 int stride, const DevCoef* __restrict__ cf) {
   const int x = blockIdx.x * 256 + threadIdx.x;
@@ -43,7 +38,7 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ fin, T* __
   T f[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) f[j] = fin[(int64_t)j * stride + x];
-  collide<Q, D, T, A>(f, CoefView<A>::relax(cf), CoefView<A>::w0(cf));
+  collide_node<Q, D, P, T, A>(f, Relax<T, A>::coef(cf), Relax<T, A>::w0(cf), cf);
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     int y = x + velocity(j);
@@ -67,13 +62,13 @@ __device__ __forceinline__ int wrapn(int y, int n) {
   return y;
 }
 
-template <int Q, int D, typename T, typename A>
+template <int Q, int D, int P, typename T, typename A>
 __device__ void resident_instance(T* __restrict__ S, T* __restrict__ g, int n, int stride, int steps,
                                   const DevCoef* __restrict__ cf, int* __restrict__ status) {
   const int B = blockDim.x;
   const int t = threadIdx.x;
-  const A* __restrict__ wg = CoefView<A>::relax(cf);
-  const A w0 = CoefView<A>::w0(cf);
+  const A* __restrict__ wg = Relax<T, A>::coef(cf);
+  const A w0 = Relax<T, A>::w0(cf);
   constexpr int H = Q / 2;   // largest |e_j|
 
   for (int j = 0; j < Q; ++j)
@@ -86,26 +81,29 @@ __device__ void resident_instance(T* __restrict__ S, T* __restrict__ g, int n, i
         T f[Q];
 #pragma unroll
         for (int j = 0; j < Q; ++j) f[j] = S[j * n + x];
-        collide<Q, D, T, A>(f, wg, w0);
+        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
 #pragma unroll
         for (int j = 0; j < Q; ++j) S[opposite(j) * n + x] = f[j];
       }
     } else {
-      for (int x = t; x < n; x += B) {
+      // interior nodes: no wrap
+      for (int x = H + t; x < n - H; x += B) {
         T f[Q];
-        if (x >= H && x < n - H) {
 #pragma unroll
-          for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * n + x - velocity(j)];
-          collide<Q, D, T, A>(f, wg, w0);
+        for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * n + x - velocity(j)];
+        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
 #pragma unroll
-          for (int j = 0; j < Q; ++j) S[j * n + x + velocity(j)] = f[j];
-        } else {
+        for (int j = 0; j < Q; ++j) S[j * n + x + velocity(j)] = f[j];
+      }
+      // the 2H nodes next to the periodic seam, one per thread
+      if (t < 2 * H) {
+        const int x = t < H ? t : n - 2 * H + t;
+        T f[Q];
 #pragma unroll
-          for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * n + wrapn(x - velocity(j), n)];
-          collide<Q, D, T, A>(f, wg, w0);
+        for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * n + wrapn(x - velocity(j), n)];
+        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
 #pragma unroll
-          for (int j = 0; j < Q; ++j) S[j * n + wrapn(x + velocity(j), n)] = f[j];
-        }
+        for (int j = 0; j < Q; ++j) S[j * n + wrapn(x + velocity(j), n)] = f[j];
       }
     }
     __syncthreads();
@@ -151,11 +149,11 @@ __global__ __launch_bounds__(256) void k_resident(const DevInst* __restrict__ it
     const DevCoef* cf = coefs + it.inst;
     int* st = status + it.inst;
     switch (it.degree) {
-#define LBM_CASE(DD) \
-  case DD:           \
-    resident_instance<Q, DD, T, A>(L, g, it.n, it.stride, it.steps, cf, st); \
+#define LBM_CASE(DD, PP)                                                             \
+  case DD | (PP << 8):                                                               \
+    resident_instance<Q, DD, PP, T, A>(L, g, it.n, it.stride, it.steps, cf, st); \
     break;
-      LBM_DEGREE_CASES(Q)
+      LBM_VARIANT_CASES
 #undef LBM_CASE
       default:
         break;
@@ -208,22 +206,22 @@ hipError_t launch_init_q(int D, const double* phi, T* f, int n, int stride, cons
   case DD:           \
     k_init<Q, DD, T><<<grid, 256, 0, s>>>(phi, f, n, stride, cf); \
     return hipGetLastError();
-    LBM_DEGREE_CASES(Q)
+    LBM_INIT_CASES
 #undef LBM_CASE
   }
   return hipErrorInvalidValue;
 }
 
 template <int Q, typename T, typename A>
-hipError_t launch_stream_q(int D, const T* fin, T* fout, int n, int stride, const DevCoef* cf,
+hipError_t launch_stream_q(int code, const T* fin, T* fout, int n, int stride, const DevCoef* cf,
                            hipStream_t s) {
   dim3 grid((n + 255) / 256);
-  switch (D) {
-#define LBM_CASE(DD) \
-  case DD:           \
-    k_stream<Q, DD, T, A><<<grid, 256, 0, s>>>(fin, fout, n, stride, cf); \
+  switch (code) {
+#define LBM_CASE(DD, PP)                                                         \
+  case DD | (PP << 8):                                                           \
+    k_stream<Q, DD, PP, T, A><<<grid, 256, 0, s>>>(fin, fout, n, stride, cf); \
     return hipGetLastError();
-    LBM_DEGREE_CASES(Q)
+    LBM_VARIANT_CASES
 #undef LBM_CASE
   }
   return hipErrorInvalidValue;
@@ -255,6 +253,7 @@ hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n
 
 hipError_t launch_stream(int q, int D, int prec, const void* fin, void* fout, int n, int stride,
                          const DevCoef* cf, hipStream_t s) {
+  // D carries the variant code (degree | parity << 8)
   if (prec == 0)
     return q == 5 ? launch_stream_q<5, double, double>(D, (const double*)fin, (double*)fout, n, stride, cf, s)
                   : launch_stream_q<7, double, double>(D, (const double*)fin, (double*)fout, n, stride, cf, s);

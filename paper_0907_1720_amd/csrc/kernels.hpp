@@ -3,31 +3,51 @@
 
 #include "device.hpp"
 
-// Padded degrees of the equilibrium polynomials that have a kernel variant.
-// D1Q5: KdV/KS/K(2,2) 5, mKdV 9, cubic Pi 13, quartic Pi_1 up to 13;
-// D1Q7: Kawahara 7, cubic Pi 13, quartic Pi_1 19.
-#define LBM_DEGREE_CASES(Q) \
-  LBM_CASE(5)               \
-  LBM_CASE(7)               \
-  LBM_CASE(9)               \
-  LBM_CASE(13)              \
+// Kernel variants of the relaxation polynomial: (padded degree D, parity P).
+// Dense (P = 0): D1Q5 KdV/KS/K(2,2) 5, cubic Pi 13, quartic Pi_1 up to 13;
+// D1Q7 Kawahara 7, cubic Pi 13, quartic Pi_1 19.  Odd (P = 1): mKdV 9.
+#define LBM_VARIANT_CASES \
+  LBM_CASE(5, 0)          \
+  LBM_CASE(7, 0)          \
+  LBM_CASE(9, 0)          \
+  LBM_CASE(13, 0)         \
+  LBM_CASE(19, 0)         \
+  LBM_CASE(5, 1)          \
+  LBM_CASE(9, 1)          \
+  LBM_CASE(13, 1)         \
+  LBM_CASE(19, 1)
+
+// dense degrees available to the initialisation kernel
+#define LBM_INIT_CASES \
+  LBM_CASE(5)          \
+  LBM_CASE(7)          \
+  LBM_CASE(9)          \
+  LBM_CASE(13)         \
   LBM_CASE(19)
 
 namespace lbm {
 
-// smallest kernel degree >= D (0 if none)
-inline int padded_degree(int D) {
-  const int menu[] = {5, 7, 9, 13, 19};
-  for (int v : menu)
-    if (v >= D) return v;
+// smallest kernel degree >= D of the given parity (0 if none)
+inline int padded_degree(int D, int parity) {
+  const int dense[] = {5, 7, 9, 13, 19};
+  const int odd[] = {5, 9, 13, 19};
+  if (parity == 0) {
+    for (int v : dense)
+      if (v >= D) return v;
+  } else {
+    for (int v : odd)
+      if (v >= D) return v;
+  }
   return 0;
 }
+inline int variant_code(int D, int parity) { return D | (parity << 8); }
 
 // prec: 0 = FP64 storage and arithmetic; 1 = FP32 deviation storage, FP64
 // relaxation; 2 = FP32 deviation storage, FP32 relaxation.
 hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n, int stride,
                        const DevCoef* cf, hipStream_t s);
-hipError_t launch_stream(int q, int D, int prec, const void* fin, void* fout, int n, int stride,
+// `code` = variant_code(D, parity) of the relaxation polynomial
+hipError_t launch_stream(int q, int code, int prec, const void* fin, void* fout, int n, int stride,
                          const DevCoef* cf, hipStream_t s);
 hipError_t launch_resident(int q, int prec, const DevInst* items, int count, int* counter, int* slots,
                            void* state, const DevCoef* coefs, int* status, int grid, int block, size_t lds,

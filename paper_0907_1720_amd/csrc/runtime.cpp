@@ -25,13 +25,16 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxResidentGrid = 256 * 8;
+constexpr int kMaxLaunches = 32;      // resident launches per advance pass
+constexpr int kAuxStreams = 8;        // concurrent size classes
 constexpr uint64_t kMagic = 0x4c424d4850444531ull;   // "LBMHPDE1"
 
 struct HostInst {
   lbm_desc desc;
   Model mdl;
   int q = 5;
-  int D = 5;        // padded kernel degree
+  int D = 5;        // variant code of the relaxation polynomial (padded degree | parity << 8)
+  int Dinit = 5;    // padded dense degree of the initialisation polynomial
   int n = 0;
   int stride = 0;
   bool f32 = false;  // FP32 deviation storage
@@ -86,6 +89,9 @@ struct lbm_batch_s {
   size_t scratch_elems = 0;
   int* flag = nullptr;                // non-finite flag for read-outs
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t aux[kAuxStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kAuxStreams] = {};
   float last_ms = 0.0f;
   std::vector<DevCoef> hcoef;
 };
@@ -99,24 +105,32 @@ namespace {
 void fill_devcoef(const HostInst& h, DevCoef* c) {
   std::memset(c, 0, sizeof(*c));
   const Model& m = h.mdl;
+  const int parity = h.D >> 8;
   c->w0 = m.w0;
   c->w0f = (float)m.w0;
+  // FP64 relaxation table: omega * G over the kept degrees
+  for (int j = 0; j < m.q; ++j) {
+    if (parity == 0) {
+      for (int d = 0; d <= m.D; ++d) c->wc[j][d] = m.wG[j][d];
+    } else {
+      for (int d = 1, k = 0; d <= m.D; d += 2, ++k) c->wc[j][k] = m.wG[j][d];
+    }
+  }
   if (h.f32) {
     c->phi_rest = m.phi_rest;
     for (int j = 0; j < m.q; ++j) {
-      c->f_rest[j] = m.f_rest[j];
       for (int d = 0; d <= m.D; ++d) {
-        c->wG[j][d] = m.wH[j][d];
-        c->G[j][d] = m.H[j][d];
+        c->init[j][d] = m.H[j][d];
         c->wHf[j][d] = (float)m.wH[j][d];
       }
     }
+    if (h.prec == LBM_F32_DEV) {
+      c->s0 = m.phi_rest;
+      for (int j = 0; j < m.q; ++j) c->cst[j] = -m.wfrest[j];
+    }
   } else {
     for (int j = 0; j < m.q; ++j)
-      for (int d = 0; d <= m.D; ++d) {
-        c->wG[j][d] = m.wG[j][d];
-        c->G[j][d] = m.G[j][d];
-      }
+      for (int d = 0; d <= m.D; ++d) c->init[j][d] = m.G[j][d];
   }
 }
 
@@ -149,6 +163,11 @@ void destroy_batch(lbm_batch_s* b) {
   hipFree(b->flag);
   if (b->ev0) hipEventDestroy(b->ev0);
   if (b->ev1) hipEventDestroy(b->ev1);
+  for (int k = 0; k < kAuxStreams; ++k) {
+    if (b->aux[k]) hipStreamDestroy(b->aux[k]);
+    if (b->join[k]) hipEventDestroy(b->join[k]);
+  }
+  if (b->fork) hipEventDestroy(b->fork);
   delete b;
 }
 
@@ -160,12 +179,21 @@ lbm_status prepare_instances(const lbm_desc* descs, int count, std::vector<HostI
     lbm_status s = build_model(descs[i], &h.mdl);
     if (s != LBM_OK) return s;
     h.q = h.mdl.q;
-    h.D = padded_degree(h.mdl.D);
-    if (h.D == 0) return LBM_ERR_UNSUPPORTED;
-    h.n = (int)descs[i].n;
-    h.stride = (int)lbm_row_stride(descs[i].n);
     h.prec = descs[i].prec;
     h.f32 = h.prec != LBM_F64;
+    // odd equilibria (every degree with a nonzero coefficient is odd) evaluate in phi^2;
+    // the FP32 relaxation uses the shifted (dense) table
+    bool odd = h.prec != LBM_F32_DEV_ARITH32;
+    for (int j = 0; j < h.mdl.q && odd; ++j)
+      for (int d = 0; d <= h.mdl.D; d += 2)
+        if (h.mdl.G[j][d] != 0.0) odd = false;
+    const int parity = odd ? 1 : 0;
+    const int kd = padded_degree(h.mdl.D, parity);
+    h.Dinit = padded_degree(h.mdl.D, 0);
+    if (kd == 0 || h.Dinit == 0) return LBM_ERR_UNSUPPORTED;
+    h.D = variant_code(kd, parity);
+    h.n = (int)descs[i].n;
+    h.stride = (int)lbm_row_stride(descs[i].n);
   }
   return LBM_OK;
 }
@@ -199,10 +227,16 @@ lbm_status alloc_batch(lbm_batch_s* b, void* dev_buf, size_t buf_bytes) {
   const int count = (int)b->inst.size();
   if (hipMalloc(&b->coefs, sizeof(DevCoef) * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
   if (hipMalloc(&b->status, sizeof(int) * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
-  b->counters_cap = 16;   // 2 slots x up to 8 group launches
+  b->counters_cap = 2 * kMaxLaunches;   // 2 item slots x up to kMaxLaunches launches
   if (hipMalloc(&b->counter, sizeof(int) * b->counters_cap) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
-  // one queue slot per workgroup of a resident launch: grid <= CUs x 8 per launch, 2 x 8 launches in flight
-  if (hipMalloc(&b->slots, sizeof(int) * kMaxResidentGrid * 16) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  // one queue slot per workgroup of each resident launch
+  if (hipMalloc(&b->slots, sizeof(int) * kMaxResidentGrid * 2 * kMaxLaunches) != hipSuccess)
+    return LBM_ERR_OUT_OF_MEMORY;
+  for (int k = 0; k < kAuxStreams; ++k) {
+    LBM_HIP(hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking));
+    LBM_HIP(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
+  }
+  LBM_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
   b->items_cap = count;
   if (hipMalloc(&b->items, sizeof(DevInst) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
   if (hipHostMalloc((void**)&b->items_host, sizeof(DevInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
@@ -290,7 +324,7 @@ lbm_status load_phi_one(lbm_batch_s* b, int i, const double* phi, int on_device)
   h.cur = 0;
   h.steps_done = 0;
   LBM_HIP(hipMemsetAsync(b->status + i, 0, sizeof(int), b->stream));
-  LBM_HIP(launch_init(h.q, h.D, h.prec, b->scratch, state_cur(b, h), h.n, h.stride, b->coefs + i, b->stream));
+  LBM_HIP(launch_init(h.q, h.Dinit, h.prec, b->scratch, state_cur(b, h), h.n, h.stride, b->coefs + i, b->stream));
   // the scratch buffer is reused by the next call on this stream; keep order
   LBM_HIP(hipStreamSynchronize(b->stream));
   return LBM_OK;
@@ -330,45 +364,77 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   int used = 0;
   for (int qq = 0; qq < 2; ++qq) {
     for (int pr = 0; pr < 3; ++pr) {
-      const std::vector<int>& g = res[qq][pr];
+      std::vector<int> g = res[qq][pr];
       if (g.empty()) continue;
-      Launch L{qq ? 7 : 5, pr, used, 0, 0};
-      for (int i : g) {
-        const HostInst& h = b->inst[i];
-        DevInst& it = hitems[used++];
-        it.off = h.off;
-        it.n = h.n;
-        it.stride = h.stride;
-        it.steps = (int)steps[i];
-        it.degree = h.D;
-        it.q = h.q;
-        it.inst = i;
-        L.lds = std::max(L.lds, (size_t)h.q * h.n * elem_size(h));
+      // size classes: LDS bytes in (cap/2^(c+1), cap/2^c], c = 0..3, and the rest;
+      // each class is one launch with its own LDS size, so small instances get
+      // more workgroups per CU
+      auto lds_of = [&](int i) { return (size_t)b->inst[i].q * b->inst[i].n * elem_size(b->inst[i]); };
+      auto class_of = [&](int i) {
+        size_t cap = b->lim.lds_max;
+        int c = 0;
+        while (c < 4 && lds_of(i) * 2 <= cap) {
+          cap /= 2;
+          ++c;
+        }
+        return c;
+      };
+      std::stable_sort(g.begin(), g.end(), [&](int a, int c) { return class_of(a) < class_of(c); });
+      size_t pos = 0;
+      while (pos < g.size()) {
+        const int cls = class_of(g[pos]);
+        Launch L{qq ? 7 : 5, pr, used, 0, 0};
+        while (pos < g.size() && class_of(g[pos]) == cls) {
+          const int i = g[pos++];
+          const HostInst& h = b->inst[i];
+          DevInst& it = hitems[used++];
+          it.off = h.off;
+          it.n = h.n;
+          it.stride = h.stride;
+          it.steps = (int)steps[i];
+          it.degree = h.D;
+          it.q = h.q;
+          it.inst = i;
+          L.lds = std::max(L.lds, lds_of(i));
+        }
+        L.count = used - L.first;
+        // largest work first (longest-processing-time order for the queue)
+        std::stable_sort(hitems + L.first, hitems + used, [](const DevInst& a, const DevInst& c) {
+          return (int64_t)a.n * a.steps > (int64_t)c.n * c.steps;
+        });
+        if ((int)launches.size() >= kMaxLaunches) return LBM_ERR_UNSUPPORTED;
+        launches.push_back(L);
       }
-      L.count = used - L.first;
-      // largest work first (longest-processing-time order for the queue)
-      std::stable_sort(hitems + L.first, hitems + used, [](const DevInst& a, const DevInst& c) {
-        return (int64_t)a.n * a.steps > (int64_t)c.n * c.steps;
-      });
-      launches.push_back(L);
     }
   }
   LBM_HIP(hipEventRecord(b->ev0, b->stream));
   if (used) {
     DevInst* ditems = b->items + (size_t)k * b->items_cap;
-    int* counters = b->counter + k * 8;
+    int* counters = b->counter + k * kMaxLaunches;
     LBM_HIP(hipMemcpyAsync(ditems, hitems, sizeof(DevInst) * used, hipMemcpyHostToDevice, b->stream));
-    LBM_HIP(hipMemsetAsync(counters, 0, sizeof(int) * 8, b->stream));
+    LBM_HIP(hipMemsetAsync(counters, 0, sizeof(int) * kMaxLaunches, b->stream));
+    // fork the size classes onto the auxiliary streams, join back afterwards
+    const bool fork = launches.size() > 1;
+    if (fork) LBM_HIP(hipEventRecord(b->fork, b->stream));
     for (size_t l = 0; l < launches.size(); ++l) {
       const Launch& L = launches[l];
+      hipStream_t st = fork ? b->aux[l % kAuxStreams] : b->stream;
+      if (fork && l < (size_t)kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
       int per_cu = 0;
       LBM_HIP(resident_occupancy(L.q, L.prec, kBlock, L.lds, &per_cu));
       if (per_cu < 1) return LBM_ERR_UNSUPPORTED;
       const int grid = std::min<int>(std::min<int>(L.count, per_cu * b->lim.cus), kMaxResidentGrid);
       void* base = L.prec ? (void*)b->f32[0] : (void*)b->f64[0];
-      int* slots = b->slots + (size_t)(k * 8 + l) * kMaxResidentGrid;
+      int* slots = b->slots + (size_t)(k * kMaxLaunches + l) * kMaxResidentGrid;
       LBM_HIP(launch_resident(L.q, L.prec, ditems + L.first, L.count, counters + l, slots, base, b->coefs,
-                              b->status, grid, kBlock, L.lds, b->stream));
+                              b->status, grid, kBlock, L.lds, st));
+    }
+    if (fork) {
+      const int nst = std::min<int>((int)launches.size(), kAuxStreams);
+      for (int a = 0; a < nst; ++a) {
+        LBM_HIP(hipEventRecord(b->join[a], b->aux[a]));
+        LBM_HIP(hipStreamWaitEvent(b->stream, b->join[a], 0));
+      }
     }
   }
   LBM_HIP(hipEventRecord(b->items_done[k], b->stream));
