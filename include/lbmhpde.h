@@ -130,10 +130,17 @@ lbm_status lbm_state_bytes(lbm_problem h, size_t* bytes);
 lbm_status lbm_save_f(lbm_problem h, void* host_buf, size_t bytes);
 lbm_status lbm_load_f(lbm_problem h, const void* host_buf, size_t bytes);
 
-/* Kernel path for lbm_advance: 0 = automatic, 1 = HBM streaming (one fused
+/* Kernel path for lbm_advance: 0 = automatic (resident when the state fits one
+   workgroup's LDS, else temporal blocking), 1 = HBM streaming (one fused
    collide+stream launch per step), 2 = on-chip resident (all steps of a call
-   in one launch; needs the state to fit one workgroup's LDS). */
+   in one launch; UNSUPPORTED if the state does not fit), 3 = temporal blocking
+   (tiles of the grid with halos advance several steps per launch in LDS). */
 lbm_status lbm_set_path(lbm_problem h, int32_t path);
+
+/* Temporal blocking parameters: steps per launch (0 = automatic, <= 4096) and
+   the number of workgroups per CU the 160 KiB LDS is split for (0 = automatic,
+   <= 8), which sets the tile width. */
+lbm_status lbm_set_tiling(lbm_problem h, int32_t steps_per_launch, int32_t wgs_per_cu);
 
 /* Device time of the kernels of the last lbm_advance, in ms (HIP events). */
 lbm_status lbm_last_advance_ms(lbm_problem h, float* ms);
@@ -160,8 +167,12 @@ lbm_status lbm_batch_read_phi(lbm_batch b, int32_t i, double* out, lbm_status* i
 lbm_status lbm_batch_last_advance_ms(lbm_batch b, float* ms);
 
 /* Planner: 0 = automatic, 1 = force HBM streaming for every instance,
-   2 = force on-chip resident (fails with UNSUPPORTED if an instance does not fit). */
+   2 = force on-chip resident (fails with UNSUPPORTED if an instance does not fit),
+   3 = force temporal blocking. */
 lbm_status lbm_batch_set_path(lbm_batch b, int32_t path);
+
+/* Temporal blocking parameters of a batch (see lbm_set_tiling). */
+lbm_status lbm_batch_set_tiling(lbm_batch b, int32_t steps_per_launch, int32_t wgs_per_cu);
 
 lbm_status lbm_batch_destroy(lbm_batch b);
 

@@ -24,12 +24,29 @@ struct DevCoef {
 
 // Per-instance launch record of the batched kernels.
 struct DevInst {
-  int64_t off;               // element offset of row 0 in the state array of its precision
+  uint64_t addr;             // device address of row 0 of the instance's current state
   int32_t n;                 // nodes
   int32_t stride;            // row stride in elements
   int32_t steps;             // steps to run in this launch
   int32_t degree;            // kernel variant: padded degree D | (parity << 8)
   int32_t q;
+  int32_t inst;              // index into coefficients / status
+};
+
+// Tiled path: one record per tile (workgroup) and one per instance.
+struct DevTile {
+  int32_t ti;                // index into the DevTileInst table
+  int32_t x0;                // first core node
+  int32_t core;              // core nodes written back by this tile
+  int32_t pad_;
+};
+struct DevTileInst {
+  int64_t off;               // element offset of row 0 in both state buffers
+  int32_t n;
+  int32_t stride;
+  int32_t steps;             // steps of this advance (all launches)
+  int32_t cur0;              // state buffer holding the input of the first launch
+  int32_t degree;            // kernel variant code
   int32_t inst;              // index into coefficients / status
 };
 

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_resident(const DevInst* __restrict__ it
     __syncthreads();
     if (item >= count) break;
     const DevInst it = items[item];
-    T* g = state + it.off;
+    T* g = reinterpret_cast<T*>(it.addr);
     const DevCoef* cf = coefs + it.inst;
     int* st = status + it.inst;
     switch (it.degree) {
@@ -159,6 +159,96 @@ __global__ __launch_bounds__(256) void k_resident(const DevInst* __restrict__ it
         break;
     }
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Temporal blocking for instances larger than one workgroup's LDS: a tile of
+// `core` nodes plus `halo` >= s * max|e_j| nodes on each side is loaded (with
+// periodic wrap) into LDS, advanced s steps in place with the AA pattern --
+// step k updates nodes [k H, W - k H), the region whose inputs are still
+// exact -- and its core is written to the other state buffer.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wrap_any(int y, int n) {
+  y %= n;
+  return y < 0 ? y + n : y;
+}
+
+template <int Q, int D, int P, typename T, typename A>
+__device__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* __restrict__ gout, int n,
+                              int stride, int x0, int core, int halo, int steps,
+                              const DevCoef* __restrict__ cf, int* __restrict__ status) {
+  const int B = blockDim.x;
+  const int t = threadIdx.x;
+  const A* __restrict__ wg = Relax<T, A>::coef(cf);
+  const A w0 = Relax<T, A>::w0(cf);
+  constexpr int H = Q / 2;
+  const int W = core + 2 * halo;
+  for (int j = 0; j < Q; ++j)
+    for (int i = t; i < W; i += B) S[j * W + i] = gin[(int64_t)j * stride + wrap_any(x0 - halo + i, n)];
+  __syncthreads();
+  for (int s = 0; s < steps; ++s) {
+    const int lo = s * H, hi = W - s * H;
+    if ((s & 1) == 0) {
+      for (int x = lo + t; x < hi; x += B) {
+        T f[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) f[j] = S[j * W + x];
+        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) S[opposite(j) * W + x] = f[j];
+      }
+    } else {
+      for (int x = lo + t; x < hi; x += B) {
+        T f[Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * W + x - velocity(j)];
+        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) S[j * W + x + velocity(j)] = f[j];
+      }
+    }
+    __syncthreads();
+  }
+  bool bad = false;
+  const bool odd = (steps & 1) != 0;
+  for (int j = 0; j < Q; ++j) {
+    for (int i = halo + t; i < halo + core; i += B) {
+      const T v = odd ? S[opposite(j) * W + i - velocity(j)] : S[j * W + i];
+      bad |= !__builtin_isfinite(v);
+      gout[(int64_t)j * stride + x0 + (i - halo)] = v;
+    }
+  }
+  if (bad) atomicOr(status, 1);
+}
+
+// One launch = `launch`-th block of up to s steps for every tile.  Instance
+// inputs alternate between the two state buffers from launch to launch.
+template <int Q, typename T, typename A>
+__global__ __launch_bounds__(256) void k_tile(const DevTile* __restrict__ tiles, const DevTileInst* __restrict__ tinsts,
+                                              T* __restrict__ buf0, T* __restrict__ buf1, int launch, int s_per,
+                                              int halo, const DevCoef* __restrict__ coefs,
+                                              int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* S = reinterpret_cast<T*>(smem_raw);
+  const DevTile tl = tiles[blockIdx.x];
+  const DevTileInst ti = tinsts[tl.ti];
+  const int left = ti.steps - launch * s_per;
+  if (left <= 0) return;
+  const int st = left < s_per ? left : s_per;
+  const int par = ti.cur0 ^ (launch & 1);
+  const T* gin = (par ? buf1 : buf0) + ti.off;
+  T* gout = (par ? buf0 : buf1) + ti.off;
+  const DevCoef* cf = coefs + ti.inst;
+  switch (ti.degree) {
+#define LBM_CASE(DD, PP)                                                                                   \
+  case DD | (PP << 8):                                                                                     \
+    tile_instance<Q, DD, PP, T, A>(S, gin, gout, ti.n, ti.stride, tl.x0, tl.core, halo, st, cf, status + ti.inst); \
+    break;
+    LBM_VARIANT_CASES
+#undef LBM_CASE
+    default:
+      break;
   }
 }
 
@@ -279,6 +369,32 @@ size_t resident_static_lds(int q, int prec) {
   hipFuncAttributes a;
   if (hipFuncGetAttributes(&a, resident_kernel(q, prec)) != hipSuccess) return 1024;
   return a.sharedSizeBytes;
+}
+
+namespace {
+template <int Q, typename T, typename A>
+const void* tile_fn() { return (const void*)k_tile<Q, T, A>; }
+const void* tile_kernel(int q, int prec) {
+  if (q == 5) {
+    if (prec == 0) return tile_fn<5, double, double>();
+    if (prec == 1) return tile_fn<5, float, double>();
+    return tile_fn<5, float, float>();
+  }
+  if (prec == 0) return tile_fn<7, double, double>();
+  if (prec == 1) return tile_fn<7, float, double>();
+  return tile_fn<7, float, float>();
+}
+}  // namespace
+
+hipError_t launch_tile(int q, int prec, const DevTile* tiles, int ntiles, const DevTileInst* tinsts, void* buf0,
+                       void* buf1, int launch, int s_per, int halo, const DevCoef* coefs, int* status, int block,
+                       size_t lds, hipStream_t s) {
+  const void* fn = tile_kernel(q, prec);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)&tiles, (void*)&tinsts, (void*)&buf0, (void*)&buf1, (void*)&launch, (void*)&s_per,
+                  (void*)&halo,  (void*)&coefs,  (void*)&status};
+  return hipLaunchKernel(fn, dim3(ntiles), dim3(block), args, lds, s);
 }
 
 hipError_t resident_occupancy(int q, int prec, int block, size_t lds, int* blocks_per_cu) {

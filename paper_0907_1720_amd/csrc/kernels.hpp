@@ -58,5 +58,9 @@ hipError_t launch_phi(int prec, const void* f, double* phi, int n, int stride, i
                       int* nonfinite, hipStream_t s);
 hipError_t launch_sum(const double* v, int n, double* part, int nparts, hipStream_t s);
 hipError_t resident_occupancy(int q, int prec, int block, size_t lds, int* blocks_per_cu);
+// temporal blocking: launch `launch` of an advance, s_per steps per launch
+hipError_t launch_tile(int q, int prec, const DevTile* tiles, int ntiles, const DevTileInst* tinsts, void* buf0,
+                       void* buf1, int launch, int s_per, int halo, const DevCoef* coefs, int* status, int block,
+                       size_t lds, hipStream_t s);
 
 }  // namespace lbm

@@ -89,6 +89,14 @@ struct lbm_batch_s {
   size_t scratch_elems = 0;
   int* flag = nullptr;                // non-finite flag for read-outs
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // temporal blocking tables (two slots like the items)
+  DevTile* tiles = nullptr;
+  DevTile* tiles_host = nullptr;
+  int tiles_cap = 0;
+  DevTileInst* tinsts = nullptr;
+  DevTileInst* tinsts_host = nullptr;
+  int tile_steps = 0;                 // steps per tiled launch (0 = automatic)
+  int tile_wgs = 0;                   // tiled workgroups per CU the LDS budget is split for (0 = automatic)
   hipStream_t aux[kAuxStreams] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kAuxStreams] = {};
@@ -161,6 +169,10 @@ void destroy_batch(lbm_batch_s* b) {
     if (b->items_done[k]) hipEventDestroy(b->items_done[k]);
   hipFree(b->scratch);
   hipFree(b->flag);
+  hipFree(b->tiles);
+  hipFree(b->tinsts);
+  if (b->tiles_host) hipHostFree(b->tiles_host);
+  if (b->tinsts_host) hipHostFree(b->tinsts_host);
   if (b->ev0) hipEventDestroy(b->ev0);
   if (b->ev1) hipEventDestroy(b->ev1);
   for (int k = 0; k < kAuxStreams; ++k) {
@@ -237,6 +249,9 @@ lbm_status alloc_batch(lbm_batch_s* b, void* dev_buf, size_t buf_bytes) {
     LBM_HIP(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
   }
   LBM_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  if (hipMalloc(&b->tinsts, sizeof(DevTileInst) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  if (hipHostMalloc((void**)&b->tinsts_host, sizeof(DevTileInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
+    return LBM_ERR_OUT_OF_MEMORY;
   b->items_cap = count;
   if (hipMalloc(&b->items, sizeof(DevInst) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
   if (hipHostMalloc((void**)&b->items_host, sizeof(DevInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
@@ -341,17 +356,19 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   const int count = (int)b->inst.size();
   // resident groups by (q, precision); the rest streams through HBM
   std::vector<int> res[2][3];   // [q == 7][prec]
-  std::vector<int> str;
+  std::vector<int> str;          // one launch per step (the plain path)
+  std::vector<int> til[2][3];    // temporal blocking, by (q, prec)
   for (int i = 0; i < count; ++i) {
     if (steps[i] == 0) continue;
     const HostInst& h = b->inst[i];
-    bool resident = fits_resident(b, h);
-    if (b->path == 1) resident = false;
-    if (b->path == 2 && !resident) return LBM_ERR_UNSUPPORTED;
-    if (resident)
-      res[h.q == 7][h.prec].push_back(i);
-    else
+    const bool fits = fits_resident(b, h);
+    if (b->path == 2 && !fits) return LBM_ERR_UNSUPPORTED;
+    if (b->path == 1)
       str.push_back(i);
+    else if (b->path == 3 || !fits)
+      til[h.q == 7][h.prec].push_back(i);
+    else
+      res[h.q == 7][h.prec].push_back(i);
   }
   // item records of this call go to slot `k`; wait until the copy issued from
   // the same slot two calls ago has been consumed
@@ -388,7 +405,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
           const int i = g[pos++];
           const HostInst& h = b->inst[i];
           DevInst& it = hitems[used++];
-          it.off = h.off;
+          it.addr = (uint64_t)(uintptr_t)state_cur(b, h);
           it.n = h.n;
           it.stride = h.stride;
           it.steps = (int)steps[i];
@@ -407,19 +424,103 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       }
     }
   }
+  // temporal blocking plan per (q, prec) group
+  struct TileGroup { int q; int prec; int first, ntiles, tfirst, tcount, s, halo, launches; size_t lds; };
+  std::vector<TileGroup> tgroups;
+  std::vector<DevTile> tvec;
+  DevTileInst* htin = b->tinsts_host + (size_t)k * count;
+  int tin_used = 0;
+  for (int qq = 0; qq < 2; ++qq) {
+    for (int pr = 0; pr < 3; ++pr) {
+      const std::vector<int>& g = til[qq][pr];
+      if (g.empty()) continue;
+      const int q = qq ? 7 : 5, H = q / 2;
+      const size_t es = pr ? sizeof(float) : sizeof(double);
+      const int wgs = b->tile_wgs > 0 ? b->tile_wgs : 2;
+      const int W = (int)(b->lim.lds_max / (size_t)wgs / (q * es));
+      int sp = b->tile_steps > 0 ? b->tile_steps : 32;
+      while (sp > 1 && W - 2 * sp * H < 2 * sp * H) sp /= 2;
+      const int halo = sp * H;
+      const int core = std::max(1, W - 2 * halo);
+      TileGroup G{q, pr, (int)tvec.size(), 0, tin_used, 0, sp, halo, 0, 0};
+      int64_t maxsteps = 0;
+      int maxcore = 1;
+      for (int i : g) {
+        const HostInst& h = b->inst[i];
+        DevTileInst& ti = htin[tin_used];
+        ti.off = h.off;
+        ti.n = h.n;
+        ti.stride = h.stride;
+        ti.steps = (int)steps[i];
+        ti.cur0 = h.cur;
+        ti.degree = h.D;
+        ti.inst = i;
+        const int c = std::min(core, h.n);
+        for (int x0 = 0; x0 < h.n; x0 += c) {
+          DevTile t{tin_used, x0, std::min(c, h.n - x0), 0};
+          tvec.push_back(t);
+        }
+        maxcore = std::max(maxcore, c);
+        maxsteps = std::max<int64_t>(maxsteps, steps[i]);
+        ++tin_used;
+      }
+      G.ntiles = (int)tvec.size() - G.first;
+      G.tcount = tin_used - G.tfirst;
+      G.launches = (int)((maxsteps + sp - 1) / sp);
+      G.lds = (size_t)q * (maxcore + 2 * halo) * es;
+      tgroups.push_back(G);
+    }
+  }
+  if (!tvec.empty()) {
+    if ((int)tvec.size() > b->tiles_cap) {
+      // grow the tile tables (both slots); previous users of the buffers must be done
+      LBM_HIP(hipStreamSynchronize(b->stream));
+      hipFree(b->tiles);
+      if (b->tiles_host) hipHostFree(b->tiles_host);
+      b->tiles = nullptr;
+      b->tiles_host = nullptr;
+      b->tiles_cap = 0;
+      const int cap = (int)tvec.size() * 2;
+      if (hipMalloc(&b->tiles, sizeof(DevTile) * 2 * cap) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+      if (hipHostMalloc((void**)&b->tiles_host, sizeof(DevTile) * 2 * cap, hipHostMallocDefault) != hipSuccess)
+        return LBM_ERR_OUT_OF_MEMORY;
+      b->tiles_cap = cap;
+    }
+    std::memcpy(b->tiles_host + (size_t)k * b->tiles_cap, tvec.data(), sizeof(DevTile) * tvec.size());
+    for (int i : str) (void)i;
+    for (int qq = 0; qq < 2; ++qq)
+      for (int pr = 0; pr < 3; ++pr) {
+        lbm_status st = til[qq][pr].empty() ? LBM_OK : ensure_second_buffer(b, pr != 0);
+        if (st != LBM_OK) return st;
+      }
+  }
+
   LBM_HIP(hipEventRecord(b->ev0, b->stream));
+  if (!tvec.empty()) {
+    DevTile* dt = b->tiles + (size_t)k * b->tiles_cap;
+    DevTileInst* dti = b->tinsts + (size_t)k * count;
+    LBM_HIP(hipMemcpyAsync(dt, b->tiles_host + (size_t)k * b->tiles_cap, sizeof(DevTile) * tvec.size(),
+                           hipMemcpyHostToDevice, b->stream));
+    LBM_HIP(hipMemcpyAsync(dti, htin, sizeof(DevTileInst) * tin_used, hipMemcpyHostToDevice, b->stream));
+  }
+  DevInst* ditems = b->items + (size_t)k * b->items_cap;
+  int* counters = b->counter + k * kMaxLaunches;
   if (used) {
-    DevInst* ditems = b->items + (size_t)k * b->items_cap;
-    int* counters = b->counter + k * kMaxLaunches;
     LBM_HIP(hipMemcpyAsync(ditems, hitems, sizeof(DevInst) * used, hipMemcpyHostToDevice, b->stream));
     LBM_HIP(hipMemsetAsync(counters, 0, sizeof(int) * kMaxLaunches, b->stream));
-    // fork the size classes onto the auxiliary streams, join back afterwards
-    const bool fork = launches.size() > 1;
-    if (fork) LBM_HIP(hipEventRecord(b->fork, b->stream));
-    for (size_t l = 0; l < launches.size(); ++l) {
+  }
+  // every resident class launch and every tiled group is a lane on an auxiliary
+  // stream; the fork is recorded after all table uploads above
+  const int lanes = (int)launches.size() + (int)tgroups.size();
+  const bool fork = lanes > 1;
+  if (fork) LBM_HIP(hipEventRecord(b->fork, b->stream));
+  int lane = 0;
+  auto lane_stream = [&](int l) -> hipStream_t { return fork ? b->aux[l % kAuxStreams] : b->stream; };
+  if (used) {
+    for (size_t l = 0; l < launches.size(); ++l, ++lane) {
       const Launch& L = launches[l];
-      hipStream_t st = fork ? b->aux[l % kAuxStreams] : b->stream;
-      if (fork && l < (size_t)kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
+      hipStream_t st = lane_stream(lane);
+      if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
       int per_cu = 0;
       LBM_HIP(resident_occupancy(L.q, L.prec, kBlock, L.lds, &per_cu));
       if (per_cu < 1) return LBM_ERR_UNSUPPORTED;
@@ -429,12 +530,29 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       LBM_HIP(launch_resident(L.q, L.prec, ditems + L.first, L.count, counters + l, slots, base, b->coefs,
                               b->status, grid, kBlock, L.lds, st));
     }
-    if (fork) {
-      const int nst = std::min<int>((int)launches.size(), kAuxStreams);
-      for (int a = 0; a < nst; ++a) {
-        LBM_HIP(hipEventRecord(b->join[a], b->aux[a]));
-        LBM_HIP(hipStreamWaitEvent(b->stream, b->join[a], 0));
-      }
+  }
+  for (const TileGroup& G : tgroups) {
+    hipStream_t st = lane_stream(lane);
+    if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
+    ++lane;
+    DevTile* dt = b->tiles + (size_t)k * b->tiles_cap + G.first;
+    DevTileInst* dti = b->tinsts + (size_t)k * count;
+    void* b0 = G.prec ? (void*)b->f32[0] : (void*)b->f64[0];
+    void* b1 = G.prec ? (void*)b->f32[1] : (void*)b->f64[1];
+    for (int l = 0; l < G.launches; ++l)
+      LBM_HIP(launch_tile(G.q, G.prec, dt, G.ntiles, dti, b0, b1, l, G.s, G.halo, b->coefs, b->status, kBlock, G.lds,
+                          st));
+    for (int t = G.tfirst; t < G.tfirst + G.tcount; ++t) {
+      HostInst& h = b->inst[htin[t].inst];
+      const int L = (int)((htin[t].steps + G.s - 1) / G.s);
+      h.cur = htin[t].cur0 ^ (L & 1);
+    }
+  }
+  if (fork) {
+    const int nst = std::min<int>(lanes, kAuxStreams);
+    for (int a = 0; a < nst; ++a) {
+      LBM_HIP(hipEventRecord(b->join[a], b->aux[a]));
+      LBM_HIP(hipStreamWaitEvent(b->stream, b->join[a], 0));
     }
   }
   LBM_HIP(hipEventRecord(b->items_done[k], b->stream));
@@ -652,7 +770,7 @@ lbm_status lbm_load_f(lbm_problem h, const void* host_buf, size_t bytes) {
 }
 
 lbm_status lbm_set_path(lbm_problem h, int32_t path) {
-  if (!h || path < 0 || path > 2) return LBM_ERR_INVALID_ARG;
+  if (!h || path < 0 || path > 3) return LBM_ERR_INVALID_ARG;
   h->b->path = path;
   return LBM_OK;
 }
@@ -704,9 +822,22 @@ lbm_status lbm_batch_last_advance_ms(lbm_batch b, float* ms) {
 }
 
 lbm_status lbm_batch_set_path(lbm_batch b, int32_t path) {
-  if (!b || path < 0 || path > 2) return LBM_ERR_INVALID_ARG;
+  if (!b || path < 0 || path > 3) return LBM_ERR_INVALID_ARG;
   b->path = path;
   return LBM_OK;
+}
+
+lbm_status lbm_batch_set_tiling(lbm_batch b, int32_t steps_per_launch, int32_t wgs_per_cu) {
+  if (!b || steps_per_launch < 0 || steps_per_launch > 4096 || wgs_per_cu < 0 || wgs_per_cu > 8)
+    return LBM_ERR_INVALID_ARG;
+  b->tile_steps = steps_per_launch;
+  b->tile_wgs = wgs_per_cu;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_tiling(lbm_problem h, int32_t steps_per_launch, int32_t wgs_per_cu) {
+  if (!h) return LBM_ERR_INVALID_ARG;
+  return lbm_batch_set_tiling(h->b, steps_per_launch, wgs_per_cu);
 }
 
 lbm_status lbm_batch_destroy(lbm_batch b) {

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmhpde.so")
 
 OK, INVALID_ARG, UNSUPPORTED, SINGULAR_TAU, OUT_OF_MEMORY, DEVICE, NONFINITE, BUSY = range(8)
-PATH_AUTO, PATH_STREAM, PATH_RESIDENT = 0, 1, 2
+PATH_AUTO, PATH_STREAM, PATH_RESIDENT, PATH_TILED = 0, 1, 2, 3
 
 
 class LbmDesc(ctypes.Structure):
@@ -76,6 +76,7 @@ def library() -> ctypes.CDLL:
         "lbm_save_f": (I32, [P, P, SZ]),
         "lbm_load_f": (I32, [P, P, SZ]),
         "lbm_set_path": (I32, [P, I32]),
+        "lbm_set_tiling": (I32, [P, I32, I32]),
         "lbm_last_advance_ms": (I32, [P, P]),
         "lbm_destroy": (I32, [P]),
         "lbm_batch_create": (I32, [DP, I32, P, P]),
@@ -84,6 +85,7 @@ def library() -> ctypes.CDLL:
         "lbm_batch_read_phi": (I32, [P, I32, P, P]),
         "lbm_batch_last_advance_ms": (I32, [P, P]),
         "lbm_batch_set_path": (I32, [P, I32]),
+        "lbm_batch_set_tiling": (I32, [P, I32, I32]),
         "lbm_batch_destroy": (I32, [P]),
     }
     for name, (res, args) in sig.items():
@@ -216,6 +218,9 @@ class Solver:
     def set_path(self, path: int):
         _check(library().lbm_set_path(self._h, int(path)), "lbm_set_path")
 
+    def set_tiling(self, steps_per_launch: int = 0, wgs_per_cu: int = 0):
+        _check(library().lbm_set_tiling(self._h, int(steps_per_launch), int(wgs_per_cu)), "lbm_set_tiling")
+
     def last_advance_ms(self) -> float:
         ms = ctypes.c_float()
         _check(library().lbm_last_advance_ms(self._h, ctypes.byref(ms)), "lbm_last_advance_ms")
@@ -270,6 +275,10 @@ class Batch:
 
     def set_path(self, path: int):
         _check(library().lbm_batch_set_path(self._h, int(path)), "lbm_batch_set_path")
+
+    def set_tiling(self, steps_per_launch: int = 0, wgs_per_cu: int = 0):
+        _check(library().lbm_batch_set_tiling(self._h, int(steps_per_launch), int(wgs_per_cu)),
+               "lbm_batch_set_tiling")
 
     def last_advance_ms(self) -> float:
         ms = ctypes.c_float()

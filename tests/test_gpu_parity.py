@@ -111,6 +111,35 @@ def test_ragged_sizes(n, kind):
         assert rel2(got, want) <= FP64_TOL, path
 
 
+@pytest.mark.parametrize("n,steps,s_per", [(257, 37, 8), (1000, 64, 16), (4099, 45, 32), (64, 9, 4), (5, 7, 2)])
+@pytest.mark.parametrize("kind", ["kdv", "kawahara", "mkdv"])
+def test_tiled_path_bitwise_equals_resident_and_stream(n, steps, s_per, kind):
+    if kind == "kawahara" and n < 7:
+        pytest.skip("D1Q7 needs n >= 7")
+    if kind == "kdv":
+        p = W.kdv(0.5, n, 0.1, 1e-4, 2.0, 0.0)
+    elif kind == "mkdv":
+        p = W.mkdv(0.7, n, 0.1, 1e-4, 2.0, 0.0)
+    else:
+        p = W.kawahara(n, 0.1, 2e-5, 3.0, 0.0)
+    phi0 = _smooth_phi(n, n + 1)
+    say("case tiled", kind, n, steps, s_per)
+    outs = {}
+    for path in (lbm.PATH_STREAM, lbm.PATH_TILED, lbm.PATH_RESIDENT):
+        if path == lbm.PATH_RESIDENT and p.lattice() * n * 8 > LDS_BYTES:
+            continue
+        s = lbm.Solver(p)
+        s.set_path(path)
+        s.set_tiling(s_per, 4)
+        s.load_phi(phi0)
+        s.advance(steps)
+        outs[path] = s.read_phi()
+        s.close()
+    for path, v in outs.items():
+        assert np.array_equal(v, outs[lbm.PATH_STREAM]), path
+    assert rel2(outs[lbm.PATH_TILED], O.run(p, phi0, steps)) <= FP64_TOL
+
+
 def test_resident_path_refuses_what_does_not_fit():
     p = W.kdv(0.5, 4099, 0.1, 1e-4, 2.0, 0.0)      # 5 * 4099 * 8 bytes > 160 KiB
     s = lbm.Solver(p)
@@ -210,6 +239,22 @@ def test_batch_streaming_path_bitwise_equals_resident():
 # ---------------------------------------------------------------------------
 # config 3: Kuramoto-Sivashinsky at the three grid sizes (short horizon sample)
 # ---------------------------------------------------------------------------
+
+def test_large_instances_batch_tiled_matches_oracle():
+    """N = 8192 (KS) and 16384 (Kawahara, K(2,2)) exceed one workgroup's LDS: the
+    automatic plan advances them by temporal blocking, several at once."""
+    insts = [W.config3_instance(8192, 1), W.config4_instance(1), W.config4_instance(3)]
+    steps = [301, 257, 190]
+    say("case large batch", [i.problem.n for i in insts], steps)
+    b = lbm.Batch([i.problem for i in insts])
+    b.load_phi([i.phi0 for i in insts])
+    b.advance(steps)
+    for k, inst in enumerate(insts):
+        got, st = b.read_phi(k)
+        assert st == lbm.OK
+        assert rel2(got, O.run(inst.problem, inst.phi0, steps[k])) <= FP64_TOL, k
+    b.close()
+
 
 @pytest.mark.parametrize("n", [1024, 4096, 8192])
 def test_config3_ks_sample(n):
