@@ -14,6 +14,8 @@ Reported:
   roofline              the dominant kernel (the persistent LDS-resident batch
                         kernel) against the VALU peak, timed with HIP events on
                         the launch stream
+  serving               p50/p99 latency and throughput of a Poisson stream of
+                        mixed solve requests through the continuous-batching server
   cpu_baseline          the CPU oracle on a sample of the same instances
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -81,6 +83,10 @@ def main():
     ap.add_argument("--count", type=int, default=COUNT)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=8)
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=256.0)
+    ap.add_argument("--serve-block", type=int, default=1000)
+    ap.add_argument("--serve-budget-gb", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the instances are independent, so several GPUs would each "
@@ -144,6 +150,15 @@ def main():
         s.close()
     plain = nu / secs
 
+    # serving: Poisson arrivals of the mixed request stream (7 equation families,
+    # N log-uniform [128, 16384], steps log-uniform [1e3, 1e5], FP32/FP64)
+    from paper_0907_1720_amd import serving
+    reqs = [W.serving_request(i) for i in range(args.serve_requests)]
+    srv = lbm.Server(args.serve_budget_gb << 30, max_slots=1024, max_n=16384, block_steps=args.serve_block,
+                     stream=stream.cuda_stream)
+    srv_out = serving.run_poisson(srv, reqs, rate=args.serve_rate, seed=1)
+    srv.close()
+
     k_ms = float(np.mean(r32["kernel_ms"]))
     achieved = r32["flops_pass"] / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
@@ -174,6 +189,11 @@ def main():
         "speedup_vs_plain_fp64": r32["nu_per_s"] / plain,
         "status_ok": bool(r32["status_ok"] and r64["status_ok"]),
         "roofline": roofline,
+        "serving": {"requests": srv_out["requests"], "arrival_rate_per_s": srv_out["rate_per_s"],
+                    "p50_latency_s": srv_out["p50_latency_s"], "p99_latency_s": srv_out["p99_latency_s"],
+                    "node_updates_per_s": srv_out["node_updates_per_s"], "wall_s": srv_out["wall_s"],
+                    "nonfinite": srv_out["nonfinite"], "block_steps": args.serve_block,
+                    "budget_bytes": args.serve_budget_gb << 30},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

@@ -100,6 +100,16 @@ lbm_status lbm_validate(const lbm_desc* d);
 lbm_status lbm_coefficients(const lbm_desc* d, double* G, int32_t cap, int32_t* q_out,
                             int32_t* degree_out);
 
+/* Host-only linear (von Neumann) pre-check: the largest growth factor per step
+   over Fourier modes kappa in (0, pi] of the scheme linearised about uniform
+   states in [phi_min, phi_max] (the eigenvalues of the q x q one-step symbol
+   E(kappa)((1 - 1/tau) I + (1/tau) f_eq'(phi) 1^T)), and its steps-th power.
+   Physical growth (e.g. the unstable band of Kuramoto-Sivashinsky) is
+   included; a value far above 1 on the grid scale marks parameters (dx, dt,
+   tau) on which the scheme itself amplifies. */
+lbm_status lbm_stability(const lbm_desc* d, double phi_min, double phi_max, int64_t steps,
+                         double* growth_per_step, double* amplification);
+
 /* ---- single problem ---------------------------------------------------- */
 
 /* Device bytes of the state of one problem (f, one buffer; plus scratch). */
@@ -175,6 +185,37 @@ lbm_status lbm_batch_set_path(lbm_batch b, int32_t path);
 lbm_status lbm_batch_set_tiling(lbm_batch b, int32_t steps_per_launch, int32_t wgs_per_cu);
 
 lbm_status lbm_batch_destroy(lbm_batch b);
+
+/* ---- serving: continuous batching of solve requests -------------------- */
+
+/* A server owns two mirrored device arenas of budget_bytes each (the state and
+   the second buffer of the tiled path), at most max_slots active requests of
+   at most max_n nodes, and advances active requests block_steps steps per
+   scheduling round.  Requests share one planner pass per round, so their work
+   overlaps on the device. */
+lbm_status lbm_server_create(void* stream, size_t budget_bytes, int32_t max_slots, int64_t max_n,
+                             int32_t block_steps, lbm_server* out);
+
+/* Queue a request (validated now; phi0 is copied).  *id >= 1.  A request whose
+   state alone exceeds the budget is refused with LBM_ERR_OUT_OF_MEMORY. */
+lbm_status lbm_server_submit(lbm_server s, const lbm_desc* d, const double* phi0, int64_t steps,
+                             int64_t* id);
+
+/* One round: admit queued requests in arrival order while a slot and arena
+   space are free (f := f_eq(phi0)), advance every active request by
+   min(block_steps, remaining) steps, retire finished requests (phi read out,
+   space released).  Synchronises the stream.  Counts are optional outputs. */
+lbm_status lbm_server_step(lbm_server s, int32_t* active, int32_t* queued, int32_t* retired);
+
+/* Result of request id: LBM_OK with phi in out[0..n) (n >= the request's node
+   count) and its own status (LBM_OK / LBM_ERR_NONFINITE) once retired;
+   LBM_ERR_BUSY while queued or running.  A result is delivered once. */
+lbm_status lbm_server_poll(lbm_server s, int64_t id, double* out, int64_t n, lbm_status* inst_status);
+
+/* Totals since creation: node updates advanced, device ms of the rounds, free arena bytes. */
+lbm_status lbm_server_stats(lbm_server s, double* node_updates, double* device_ms, size_t* free_bytes);
+
+lbm_status lbm_server_destroy(lbm_server s);
 
 #ifdef __cplusplus
 }

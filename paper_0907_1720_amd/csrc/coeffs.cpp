@@ -320,3 +320,95 @@ void set_rest_state(Model* mdl, double phi_rest) {
 }
 
 }  // namespace lbm
+
+// ---------------------------------------------------------------------------
+// Linear (von Neumann) stability of the scheme about a uniform state phi_bar:
+// f_eq(phi_bar + d) ~ f_eq(phi_bar) + w d with w_j = f_eq_j'(phi_bar), so one
+// step acts on a Fourier mode exp(i kappa x) as A = E ((1 - omega) I + omega w 1^T),
+// E = diag(exp(-i kappa e_j)).  A is a rank-one update of a diagonal matrix; its
+// eigenvalues are the roots of
+//   P(lam) = prod_j (lam - c E_j) - omega sum_j E_j w_j prod_{l != j} (lam - c E_l),
+// c = 1 - omega, found by Durand-Kerner iteration.
+// ---------------------------------------------------------------------------
+#include <complex>
+
+namespace lbm {
+namespace {
+using cld = std::complex<long double>;
+
+// coefficients (ascending) of prod over roots r of (lam - r)
+void poly_from_roots(const cld* r, int m, cld* out) {
+  for (int i = 0; i <= m; ++i) out[i] = 0;
+  out[0] = 1;
+  int deg = 0;
+  for (int k = 0; k < m; ++k) {
+    for (int i = deg + 1; i >= 1; --i) out[i] = out[i - 1] - r[k] * out[i];
+    out[0] = -r[k] * out[0];
+    ++deg;
+  }
+}
+
+long double spectral_radius(const Model& m, const long double* w, long double kappa) {
+  const int q = m.q;
+  const long double omega = 1.0L / (long double)m.tau, c = 1.0L - omega;
+  cld E[kMaxQ], P[kMaxQ + 1], T[kMaxQ + 1], r[kMaxQ];
+  for (int j = 0; j < q; ++j) E[j] = std::polar(1.0L, -kappa * kVelocity[j]);
+  for (int j = 0; j < q; ++j) r[j] = c * E[j];
+  poly_from_roots(r, q, P);
+  for (int j = 0; j < q; ++j) {
+    cld rr[kMaxQ];
+    int k = 0;
+    for (int l = 0; l < q; ++l)
+      if (l != j) rr[k++] = c * E[l];
+    poly_from_roots(rr, q - 1, T);
+    for (int i = 0; i < q; ++i) P[i] -= omega * E[j] * w[j] * T[i];
+  }
+  // Durand-Kerner on the monic polynomial P (degree q)
+  cld z[kMaxQ];
+  const cld seed(0.4L, 0.9L);
+  cld zz = 1;
+  for (int i = 0; i < q; ++i) {
+    z[i] = zz * 1.1L;
+    zz *= seed;
+  }
+  for (int it = 0; it < 500; ++it) {
+    long double move = 0;
+    for (int i = 0; i < q; ++i) {
+      cld num = P[q];
+      for (int d = q - 1; d >= 0; --d) num = num * z[i] + P[d];
+      cld den = 1;
+      for (int j = 0; j < q; ++j)
+        if (j != i) den *= (z[i] - z[j]);
+      if (std::abs(den) == 0) den = 1e-30L;
+      const cld dz = num / den;
+      z[i] -= dz;
+      move = std::max(move, std::abs(dz));
+    }
+    if (move < 1e-15L) break;
+  }
+  long double rad = 0;
+  for (int i = 0; i < q; ++i) rad = std::max(rad, std::abs(z[i]));
+  return rad;
+}
+}  // namespace
+
+double stability_growth(const Model& m, double phi_min, double phi_max) {
+  long double worst = 0;
+  const int nphi = 5, nk = 129;
+  for (int a = 0; a < nphi; ++a) {
+    const long double pb = phi_min + (phi_max - phi_min) * (long double)a / (nphi - 1);
+    long double w[kMaxQ];
+    for (int j = 0; j < m.q; ++j) {   // w_j = d/dphi sum_d G[j][d] phi^d at phi_bar
+      long double acc = 0;
+      for (int d = m.D; d >= 1; --d) acc = acc * pb + (long double)d * (long double)m.Gq[j][d];
+      w[j] = acc;
+    }
+    for (int k = 1; k < nk; ++k) {
+      const long double kappa = 3.14159265358979323846264L * k / (nk - 1);
+      worst = std::max(worst, spectral_radius(m, w, kappa));
+    }
+  }
+  return (double)worst;
+}
+
+}  // namespace lbm

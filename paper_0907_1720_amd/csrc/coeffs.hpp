@@ -49,4 +49,9 @@ int resolved_lattice(const lbm_desc& d);
 
 extern const int kVelocity[kMaxQ];
 
+// Largest |eigenvalue| over Fourier modes kappa in (0, pi] of the scheme
+// linearised about uniform states phi_bar in [phi_min, phi_max] (5 states,
+// 128 modes): the growth factor per step of the most amplified mode.
+double stability_growth(const Model& m, double phi_min, double phi_max);
+
 }  // namespace lbm

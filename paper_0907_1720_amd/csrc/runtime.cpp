@@ -75,6 +75,7 @@ struct lbm_batch_s {
   float* f32[2] = {nullptr, nullptr};
   size_t n64 = 0, n32 = 0;            // elements per buffer
   bool own_state = true;
+  void* arena[2] = {nullptr, nullptr};  // serving: both state buffers carved from two arenas
   DevCoef* coefs = nullptr;
   int* status = nullptr;              // per instance: 1 = non-finite seen
   int* counter = nullptr;             // work queue counters (one per group launch)
@@ -153,12 +154,17 @@ size_t elem_size(const HostInst& h) { return h.f32 ? sizeof(float) : sizeof(doub
 void destroy_batch(lbm_batch_s* b) {
   if (!b) return;
   hipStreamSynchronize(b->stream);
-  if (b->own_state) {
-    hipFree(b->f64[0]);
-    hipFree(b->f32[0]);
+  if (b->arena[0]) {
+    hipFree(b->arena[0]);
+    hipFree(b->arena[1]);
+  } else {
+    if (b->own_state) {
+      hipFree(b->f64[0]);
+      hipFree(b->f32[0]);
+    }
+    hipFree(b->f64[1]);
+    hipFree(b->f32[1]);
   }
-  hipFree(b->f64[1]);
-  hipFree(b->f32[1]);
   hipFree(b->coefs);
   hipFree(b->status);
   hipFree(b->counter);
@@ -183,32 +189,41 @@ void destroy_batch(lbm_batch_s* b) {
   delete b;
 }
 
+lbm_status prepare_one(const lbm_desc& d, HostInst* hp) {
+  HostInst& h = *hp;
+  h = HostInst();
+  h.desc = d;
+  lbm_status s = build_model(d, &h.mdl);
+  if (s != LBM_OK) return s;
+  h.q = h.mdl.q;
+  h.prec = d.prec;
+  h.f32 = h.prec != LBM_F64;
+  // odd equilibria (every degree with a nonzero coefficient is odd) evaluate in phi^2;
+  // the FP32 relaxation uses the shifted (dense) table
+  bool odd = h.prec != LBM_F32_DEV_ARITH32;
+  for (int j = 0; j < h.mdl.q && odd; ++j)
+    for (int p = 0; p <= h.mdl.D; p += 2)
+      if (h.mdl.G[j][p] != 0.0) odd = false;
+  const int parity = odd ? 1 : 0;
+  const int kd = padded_degree(h.mdl.D, parity);
+  h.Dinit = padded_degree(h.mdl.D, 0);
+  if (kd == 0 || h.Dinit == 0) return LBM_ERR_UNSUPPORTED;
+  h.D = variant_code(kd, parity);
+  h.n = (int)d.n;
+  h.stride = (int)lbm_row_stride(d.n);
+  return LBM_OK;
+}
+
 lbm_status prepare_instances(const lbm_desc* descs, int count, std::vector<HostInst>* out) {
   out->resize(count);
   for (int i = 0; i < count; ++i) {
-    HostInst& h = (*out)[i];
-    h.desc = descs[i];
-    lbm_status s = build_model(descs[i], &h.mdl);
+    lbm_status s = prepare_one(descs[i], &(*out)[i]);
     if (s != LBM_OK) return s;
-    h.q = h.mdl.q;
-    h.prec = descs[i].prec;
-    h.f32 = h.prec != LBM_F64;
-    // odd equilibria (every degree with a nonzero coefficient is odd) evaluate in phi^2;
-    // the FP32 relaxation uses the shifted (dense) table
-    bool odd = h.prec != LBM_F32_DEV_ARITH32;
-    for (int j = 0; j < h.mdl.q && odd; ++j)
-      for (int d = 0; d <= h.mdl.D; d += 2)
-        if (h.mdl.G[j][d] != 0.0) odd = false;
-    const int parity = odd ? 1 : 0;
-    const int kd = padded_degree(h.mdl.D, parity);
-    h.Dinit = padded_degree(h.mdl.D, 0);
-    if (kd == 0 || h.Dinit == 0) return LBM_ERR_UNSUPPORTED;
-    h.D = variant_code(kd, parity);
-    h.n = (int)descs[i].n;
-    h.stride = (int)lbm_row_stride(descs[i].n);
   }
   return LBM_OK;
 }
+
+lbm_status alloc_tables(lbm_batch_s* b, size_t maxn);
 
 lbm_status alloc_batch(lbm_batch_s* b, void* dev_buf, size_t buf_bytes) {
   size_t n64 = 0, n32 = 0, maxn = 0;
@@ -236,6 +251,12 @@ lbm_status alloc_batch(lbm_batch_s* b, void* dev_buf, size_t buf_bytes) {
     if (n64 && hipMalloc(&b->f64[0], n64 * sizeof(double)) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
     if (n32 && hipMalloc(&b->f32[0], n32 * sizeof(float)) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
   }
+  return alloc_tables(b, maxn);
+}
+
+// Per-instance tables, queues, streams and events for `b->inst.size()` slots;
+// read-out scratch for grids of up to maxn nodes.
+lbm_status alloc_tables(lbm_batch_s* b, size_t maxn) {
   const int count = (int)b->inst.size();
   if (hipMalloc(&b->coefs, sizeof(DevCoef) * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
   if (hipMalloc(&b->status, sizeof(int) * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
@@ -264,10 +285,6 @@ lbm_status alloc_batch(lbm_batch_s* b, void* dev_buf, size_t buf_bytes) {
   LBM_HIP(hipEventCreate(&b->ev0));
   LBM_HIP(hipEventCreate(&b->ev1));
   b->hcoef.resize(count);
-  for (int i = 0; i < count; ++i) {
-    lbm_status s = upload_coef(b, i);
-    if (s != LBM_OK) return s;
-  }
   return LBM_OK;
 }
 
@@ -287,6 +304,7 @@ lbm_status create_batch(const lbm_desc* descs, int count, void* stream, void* de
     return LBM_ERR_DEVICE;
   }
   s = alloc_batch(b, dev_buf, buf_bytes);
+  for (int i = 0; i < count && s == LBM_OK; ++i) s = upload_coef(b, i);
   if (s != LBM_OK) {
     destroy_batch(b);
     return s;
@@ -438,10 +456,16 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const size_t es = pr ? sizeof(float) : sizeof(double);
       const int wgs = b->tile_wgs > 0 ? b->tile_wgs : 2;
       const int W = (int)(b->lim.lds_max / (size_t)wgs / (q * es));
+      // tile core: as wide as the LDS share allows, but narrow enough that the
+      // group yields about 4 tiles per CU (a few large instances would otherwise
+      // leave most CUs idle); halo / core kept below 1/4
+      int64_t nodes = 0;
+      for (int i : g) nodes += b->inst[i].n;
+      const int want = (int)std::max<int64_t>(256, nodes / (4 * (int64_t)b->lim.cus));
       int sp = b->tile_steps > 0 ? b->tile_steps : 32;
-      while (sp > 1 && W - 2 * sp * H < 2 * sp * H) sp /= 2;
+      while (sp > 1 && (W - 2 * sp * H < 2 * sp * H || (b->tile_steps == 0 && 8 * sp * H > want))) sp /= 2;
       const int halo = sp * H;
-      const int core = std::max(1, W - 2 * halo);
+      const int core = std::max(1, std::min(W - 2 * halo, want));
       TileGroup G{q, pr, (int)tvec.size(), 0, tin_used, 0, sp, halo, 0, 0};
       int64_t maxsteps = 0;
       int maxcore = 1;
@@ -659,6 +683,20 @@ lbm_status lbm_coefficients(const lbm_desc* d, double* G, int32_t cap, int32_t* 
   return LBM_OK;
 }
 
+lbm_status lbm_stability(const lbm_desc* d, double phi_min, double phi_max, int64_t steps,
+                         double* growth_per_step, double* amplification) {
+  if (!d || !growth_per_step || steps < 0 || !(phi_min <= phi_max) || !std::isfinite(phi_min) ||
+      !std::isfinite(phi_max))
+    return LBM_ERR_INVALID_ARG;
+  Model m;
+  lbm_status s = build_model(*d, &m);
+  if (s != LBM_OK) return s;
+  const double g = stability_growth(m, phi_min, phi_max);
+  *growth_per_step = g;
+  if (amplification) *amplification = std::pow(g, (double)steps);
+  return LBM_OK;
+}
+
 lbm_status lbm_required_bytes(const lbm_desc* d, size_t* bytes) {
   if (!d || !bytes) return LBM_ERR_INVALID_ARG;
   Model m;
@@ -843,6 +881,276 @@ lbm_status lbm_set_tiling(lbm_problem h, int32_t steps_per_launch, int32_t wgs_p
 lbm_status lbm_batch_destroy(lbm_batch b) {
   if (!b) return LBM_ERR_INVALID_ARG;
   destroy_batch(b);
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving: continuous batching of solve requests
+// ===========================================================================
+namespace {
+
+// first-fit allocator over [0, size) in 256-byte units
+struct Arena {
+  struct Block { size_t off, len; };
+  std::vector<Block> free;
+  size_t size = 0;
+  void init(size_t bytes) {
+    size = bytes / 256 * 256;
+    free.assign(1, Block{0, size});
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = (bytes + 255) / 256 * 256;
+    for (size_t i = 0; i < free.size(); ++i) {
+      if (free[i].len >= bytes) {
+        *off = free[i].off;
+        free[i].off += bytes;
+        free[i].len -= bytes;
+        if (free[i].len == 0) free.erase(free.begin() + i);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) / 256 * 256;
+    size_t i = 0;
+    while (i < free.size() && free[i].off < off) ++i;
+    free.insert(free.begin() + i, Block{off, bytes});
+    if (i + 1 < free.size() && free[i].off + free[i].len == free[i + 1].off) {
+      free[i].len += free[i + 1].len;
+      free.erase(free.begin() + i + 1);
+    }
+    if (i > 0 && free[i - 1].off + free[i - 1].len == free[i].off) {
+      free[i - 1].len += free[i].len;
+      free.erase(free.begin() + i);
+    }
+  }
+  size_t available() const {
+    size_t t = 0;
+    for (const Block& b : free) t += b.len;
+    return t;
+  }
+};
+
+struct Request {
+  int64_t id;
+  lbm_desc desc;
+  std::vector<double> phi0;
+  int64_t steps;
+};
+
+struct Slot {
+  bool active = false;
+  int64_t id = -1;
+  int64_t remaining = 0;
+  size_t off = 0, bytes = 0;
+};
+
+struct Result {
+  std::vector<double> phi;
+  lbm_status status;
+};
+
+size_t state_bytes_of(const lbm_desc& d) {
+  const int q = resolved_lattice(d);
+  const size_t es = d.prec == LBM_F64 ? sizeof(double) : sizeof(float);
+  return (size_t)q * (size_t)lbm_row_stride(d.n) * es;
+}
+
+}  // namespace
+
+struct lbm_server_s {
+  lbm_batch_s* b = nullptr;
+  Arena arena;
+  int block = 1000;
+  int64_t max_n = 0;
+  int64_t next_id = 1;
+  std::vector<Request> queue;        // FIFO
+  std::vector<Slot> slots;
+  std::vector<Result> results;       // indexed by id - 1 (kept until polled)
+  std::vector<char> done;
+  std::vector<int64_t> steps_buf;
+  double node_updates = 0.0;
+  double device_ms = 0.0;
+};
+
+extern "C" {
+
+lbm_status lbm_server_create(void* stream, size_t budget_bytes, int32_t max_slots, int64_t max_n,
+                             int32_t block_steps, lbm_server* out) {
+  if (!out || max_slots <= 0 || max_slots > 65536 || max_n < 5 || max_n > (int64_t(1) << 30) ||
+      block_steps <= 0 || budget_bytes < 4096)
+    return LBM_ERR_INVALID_ARG;
+  lbm_server_s* sv = new (std::nothrow) lbm_server_s();
+  if (!sv) return LBM_ERR_OUT_OF_MEMORY;
+  lbm_batch_s* b = new (std::nothrow) lbm_batch_s();
+  if (!b) {
+    delete sv;
+    return LBM_ERR_OUT_OF_MEMORY;
+  }
+  sv->b = b;
+  b->stream = (hipStream_t)stream;
+  b->lim = query_limits();
+  b->inst.resize(max_slots);
+  lbm_status s = b->lim.ok ? LBM_OK : LBM_ERR_DEVICE;
+  // two mirrored arenas: the current state and the other buffer of the tiled path
+  sv->arena.init(budget_bytes);
+  for (int k = 0; k < 2 && s == LBM_OK; ++k)
+    if (hipMalloc(&b->arena[k], sv->arena.size) != hipSuccess) s = LBM_ERR_OUT_OF_MEMORY;
+  if (s == LBM_OK) {
+    b->f64[0] = (double*)b->arena[0];
+    b->f32[0] = (float*)b->arena[0];
+    b->f64[1] = (double*)b->arena[1];
+    b->f32[1] = (float*)b->arena[1];
+    b->n64 = sv->arena.size / sizeof(double);
+    b->n32 = sv->arena.size / sizeof(float);
+    s = alloc_tables(b, (size_t)max_n);
+  }
+  if (s != LBM_OK) {
+    destroy_batch(b);
+    delete sv;
+    return s;
+  }
+  sv->block = block_steps;
+  sv->max_n = max_n;
+  sv->slots.resize(max_slots);
+  sv->steps_buf.assign(max_slots, 0);
+  *out = sv;
+  return LBM_OK;
+}
+
+lbm_status lbm_server_submit(lbm_server sv, const lbm_desc* d, const double* phi0, int64_t steps, int64_t* id) {
+  if (!sv || !d || !phi0 || !id || steps < 0) return LBM_ERR_INVALID_ARG;
+  Model m;
+  lbm_status s = build_model(*d, &m);
+  if (s != LBM_OK) return s;
+  if (d->n > sv->max_n) return LBM_ERR_INVALID_ARG;
+  if (state_bytes_of(*d) > sv->arena.size) return LBM_ERR_OUT_OF_MEMORY;
+  for (int64_t i = 0; i < d->n; ++i)
+    if (!std::isfinite(phi0[i])) return LBM_ERR_INVALID_ARG;
+  Request r;
+  r.id = sv->next_id++;
+  r.desc = *d;
+  r.phi0.assign(phi0, phi0 + d->n);
+  r.steps = steps;
+  sv->queue.push_back(std::move(r));
+  sv->results.emplace_back();
+  sv->done.push_back(0);
+  *id = sv->queue.back().id;
+  return LBM_OK;
+}
+
+// One scheduling round: admit queued requests (FIFO) while a slot and arena
+// space are free, advance every active request by min(block, remaining) steps
+// in one planner pass (persistent resident launches per LDS class, tiled groups,
+// all concurrent), then retire finished requests and free their space.
+lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int32_t* retired) {
+  if (!sv) return LBM_ERR_INVALID_ARG;
+  lbm_batch_s* b = sv->b;
+  // admission
+  size_t qi = 0;
+  for (; qi < sv->queue.size(); ++qi) {
+    Request& r = sv->queue[qi];
+    int slot = -1;
+    for (size_t k = 0; k < sv->slots.size(); ++k)
+      if (!sv->slots[k].active) {
+        slot = (int)k;
+        break;
+      }
+    if (slot < 0) break;
+    const size_t bytes = state_bytes_of(r.desc);
+    size_t off = 0;
+    if (!sv->arena.alloc(bytes, &off)) break;   // FIFO: wait for space
+    HostInst& h = b->inst[slot];
+    lbm_status s = prepare_one(r.desc, &h);
+    if (s != LBM_OK) {
+      sv->arena.release(off, bytes);
+      return s;
+    }
+    h.off = (int64_t)(off / (h.f32 ? sizeof(float) : sizeof(double)));
+    s = load_phi_one(b, slot, r.phi0.data(), 0);
+    if (s != LBM_OK) {
+      sv->arena.release(off, bytes);
+      return s;
+    }
+    Slot& sl = sv->slots[slot];
+    sl.active = true;
+    sl.id = r.id;
+    sl.remaining = r.steps;
+    sl.off = off;
+    sl.bytes = bytes;
+  }
+  sv->queue.erase(sv->queue.begin(), sv->queue.begin() + qi);
+  // one block
+  int act = 0;
+  double nu = 0.0;
+  for (size_t k = 0; k < sv->slots.size(); ++k) {
+    const Slot& sl = sv->slots[k];
+    sv->steps_buf[k] = sl.active ? std::min<int64_t>(sl.remaining, sv->block) : 0;
+    if (sl.active) {
+      ++act;
+      nu += (double)sv->steps_buf[k] * b->inst[k].n;
+    }
+  }
+  if (act) {
+    lbm_status s = advance(b, sv->steps_buf.data());
+    if (s != LBM_OK) return s;
+    float ms = 0.0f;
+    LBM_HIP(hipEventSynchronize(b->ev1));
+    if (hipEventElapsedTime(&ms, b->ev0, b->ev1) == hipSuccess) sv->device_ms += ms;
+    sv->node_updates += nu;
+  }
+  // retirement
+  int ret = 0;
+  for (size_t k = 0; k < sv->slots.size(); ++k) {
+    Slot& sl = sv->slots[k];
+    if (!sl.active) continue;
+    sl.remaining -= sv->steps_buf[k];
+    if (sl.remaining > 0) continue;
+    Result& res = sv->results[sl.id - 1];
+    res.phi.resize(b->inst[k].n);
+    lbm_status st = LBM_OK;
+    lbm_status s = read_phi(b, (int)k, res.phi.data(), 0, &st);
+    if (s != LBM_OK && s != LBM_ERR_NONFINITE) return s;
+    res.status = st;
+    sv->done[sl.id - 1] = 1;
+    sv->arena.release(sl.off, sl.bytes);
+    sl = Slot();
+    ++ret;
+  }
+  if (active) *active = act - ret;
+  if (queued) *queued = (int32_t)sv->queue.size();
+  if (retired) *retired = ret;
+  return LBM_OK;
+}
+
+lbm_status lbm_server_poll(lbm_server sv, int64_t id, double* out, int64_t n, lbm_status* inst_status) {
+  if (!sv || id < 1 || id >= sv->next_id) return LBM_ERR_INVALID_ARG;
+  if (sv->done[id - 1] != 1) return sv->done[id - 1] == 2 ? LBM_ERR_INVALID_ARG : LBM_ERR_BUSY;
+  Result& r = sv->results[id - 1];
+  if (!out || n < (int64_t)r.phi.size()) return LBM_ERR_INVALID_ARG;
+  std::memcpy(out, r.phi.data(), sizeof(double) * r.phi.size());
+  if (inst_status) *inst_status = r.status;
+  r.phi.clear();
+  r.phi.shrink_to_fit();
+  sv->done[id - 1] = 2;   // delivered
+  return LBM_OK;
+}
+
+lbm_status lbm_server_stats(lbm_server sv, double* node_updates, double* device_ms, size_t* free_bytes) {
+  if (!sv) return LBM_ERR_INVALID_ARG;
+  if (node_updates) *node_updates = sv->node_updates;
+  if (device_ms) *device_ms = sv->device_ms;
+  if (free_bytes) *free_bytes = sv->arena.available();
+  return LBM_OK;
+}
+
+lbm_status lbm_server_destroy(lbm_server sv) {
+  if (!sv) return LBM_ERR_INVALID_ARG;
+  destroy_batch(sv->b);
+  delete sv;
   return LBM_OK;
 }
 

@@ -67,6 +67,7 @@ def library() -> ctypes.CDLL:
         "lbm_validate": (I32, [DP]),
         "lbm_coefficients": (I32, [DP, P, I32, P, P]),
         "lbm_required_bytes": (I32, [DP, P]),
+        "lbm_stability": (I32, [DP, D, D, I64, P, P]),
         "lbm_create": (I32, [DP, P, P, SZ, P]),
         "lbm_load_phi": (I32, [P, P, I32]),
         "lbm_advance": (I32, [P, I64]),
@@ -87,6 +88,12 @@ def library() -> ctypes.CDLL:
         "lbm_batch_set_path": (I32, [P, I32]),
         "lbm_batch_set_tiling": (I32, [P, I32, I32]),
         "lbm_batch_destroy": (I32, [P]),
+        "lbm_server_create": (I32, [P, SZ, I32, I64, I32, P]),
+        "lbm_server_submit": (I32, [P, DP, P, I64, P]),
+        "lbm_server_step": (I32, [P, P, P, P]),
+        "lbm_server_poll": (I32, [P, I64, P, I64, P]),
+        "lbm_server_stats": (I32, [P, P, P, P]),
+        "lbm_server_destroy": (I32, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -143,6 +150,14 @@ def coefficients(p: Problem) -> np.ndarray:
     _check(library().lbm_coefficients(ctypes.byref(make_desc(p)), buf.ctypes.data, buf.size,
                                       ctypes.byref(q), ctypes.byref(D)), "lbm_coefficients")
     return buf[: q.value * (D.value + 1)].reshape(q.value, D.value + 1).copy()
+
+
+def stability(p: Problem, phi_min: float, phi_max: float, steps: int):
+    """(growth per step, amplification over `steps`) of the linearised scheme."""
+    g, a = ctypes.c_double(), ctypes.c_double()
+    _check(library().lbm_stability(ctypes.byref(make_desc(p)), float(phi_min), float(phi_max), int(steps),
+                                   ctypes.byref(g), ctypes.byref(a)), "lbm_stability")
+    return g.value, a.value
 
 
 def _current_stream() -> int:
@@ -288,6 +303,64 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             library().lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous batching of solve requests (lbm_server_*)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 4096, max_n: int = 16384,
+                 block_steps: int = 1000, stream: Optional[int] = None):
+        self.stream = _current_stream() if stream is None else int(stream)
+        h = ctypes.c_void_p()
+        _check(library().lbm_server_create(self.stream, int(budget_bytes), int(max_slots), int(max_n),
+                                           int(block_steps), ctypes.byref(h)), "lbm_server_create")
+        self._h = h
+        self._n = {}
+
+    def submit(self, p: Problem, phi0, steps: int) -> int:
+        a = np.ascontiguousarray(phi0, dtype=np.float64)
+        assert a.size == p.n
+        d = make_desc(p)
+        rid = ctypes.c_int64()
+        _check(library().lbm_server_submit(self._h, ctypes.byref(d), a.ctypes.data, int(steps), ctypes.byref(rid)),
+               "lbm_server_submit")
+        self._n[rid.value] = p.n
+        return rid.value
+
+    def step(self):
+        """One scheduling round; returns (active, queued, retired)."""
+        a, q, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(library().lbm_server_step(self._h, ctypes.byref(a), ctypes.byref(q), ctypes.byref(r)),
+               "lbm_server_step")
+        return a.value, q.value, r.value
+
+    def poll(self, rid: int):
+        """(phi, status) once request rid has finished, else None."""
+        n = self._n[rid]
+        out = np.empty(n, dtype=np.float64)
+        st = ctypes.c_int32()
+        s = library().lbm_server_poll(self._h, int(rid), out.ctypes.data, n, ctypes.byref(st))
+        if s == BUSY:
+            return None
+        _check(s, "lbm_server_poll")
+        return out, st.value
+
+    def stats(self):
+        nu, ms, free = ctypes.c_double(), ctypes.c_double(), ctypes.c_size_t()
+        _check(library().lbm_server_stats(self._h, ctypes.byref(nu), ctypes.byref(ms), ctypes.byref(free)),
+               "lbm_server_stats")
+        return nu.value, ms.value, free.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().lbm_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

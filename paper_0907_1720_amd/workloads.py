@@ -264,3 +264,77 @@ def random_m6_problem(g: np.random.Generator, n: int) -> Problem:
     dx = 0.1
     dt = 0.05 * min(dx ** k / abs(a[k]) for k in range(2, 7) if a[k] != 0.0)
     return Problem(tuple(a), tuple(pis), n, dx, dt, 1.5, x0=0.0, name="random_m6")
+
+
+# ---------------------------------------------------------------------------
+# serving mix: one request = (problem, phi0, steps)
+# ---------------------------------------------------------------------------
+
+SERVING_FAMILIES = ("kdv", "mkdv", "kdv_burgers", "k22", "ks", "kawahara", "random_m6")
+KS_TAU_RULE = ((2048, 2.0), (4096, 10.0), (1 << 40, 20.0))
+# KS time step dt = C(tau) dx^4; the constants reproduce the (tau, dt) settings
+# of the Kuramoto-Sivashinsky batch (2, 2.9e-4) at N = 1024, (10, 3.1e-4) at
+# N = 4096 and (20, 1.7e-4) at N = 8192 on [0, 32 pi)
+KS_DT_CONST = {2.0: 3.125, 10.0: 855.7916666666666, 20.0: 7411.625}
+
+
+def serving_request(i: int, n_min: int = 128, n_max: int = 16384, steps_min: int = 1000,
+                    steps_max: int = 100000) -> Instance:
+    """Request i of the serving mix: a uniformly drawn family, N and steps
+    log-uniform, precision FP32 deviation or FP64 with probability 1/2."""
+    g = rng(5, i)
+    fam = SERVING_FAMILIES[int(g.integers(len(SERVING_FAMILIES)))]
+    n = int(round(math.exp(g.uniform(math.log(n_min), math.log(n_max)))))
+    steps = int(round(math.exp(g.uniform(math.log(steps_min), math.log(steps_max)))))
+    prec = F32_DEV if g.random() < 0.5 else F64
+    if fam in ("kdv", "mkdv", "kdv_burgers"):
+        L = 40.0
+        dx = L / n
+        delta = float(g.uniform(0.5, 2.0))
+        c = float(g.uniform(0.2, 2.0))
+        xc = float(g.uniform(-20.0, 20.0))
+        dt = 0.05 * dx ** 3 / delta
+        if fam == "kdv":
+            p = kdv(delta, n, dx, dt, 2.0, -20.0, prec=prec)
+            phi0 = kdv_soliton(p.grid(), 0.0, c, delta, xc, period=L)
+        elif fam == "mkdv":
+            p = mkdv(delta, n, dx, dt, 2.0, -20.0, prec=prec)
+            phi0 = mkdv_soliton(p.grid(), 0.0, c, delta, xc, period=L)
+        else:
+            nu = float(g.uniform(0.01, 0.1))
+            p = kdv_burgers(nu, delta, n, dx, dt, 2.0, -20.0, prec=prec)
+            phi0 = kdv_soliton(p.grid(), 0.0, c, delta, xc, period=L)
+    elif fam == "ks":
+        # coarser grids do not resolve the KS length scales on [0, 32 pi) (and the
+        # time-step rule is unstable there): at least 1024 nodes
+        n = max(n, 1024)
+        L = 32.0 * math.pi
+        dx = L / n
+        tau = next(t for lim, t in KS_TAU_RULE if n <= lim)
+        p = kuramoto_sivashinsky(n, dx, KS_DT_CONST[tau] * dx ** 4, tau, 0.0, prec=prec)
+        x = p.grid()
+        phi0 = np.cos(x / 16.0) * (1.0 + np.sin(x / 16.0)) + g.normal(0.0, 1e-3, n)
+    elif fam in ("kawahara", "k22"):
+        L = 120.0
+        dx = L / n
+        if fam == "kawahara":
+            # the dx^5 rule of the Kawahara batch, capped at a lattice speed c >= 10;
+            # below 2048 nodes tau = 8 (at tau = 3 the grid-scale mode of coarse
+            # grids grows up to ~0.6% per step)
+            p = kawahara(n, dx, min(1.3e-5 * (dx / 0.0586) ** 5, 0.1 * dx), 3.0 if n >= 2048 else 8.0, -60.0,
+                         prec=prec)
+            phi0 = kawahara_soliton(p.grid(), 0.0, float(g.uniform(-60.0, 60.0)), period=L)
+        else:
+            # tau = 5: at the batch's tau = 2 the grid-scale mode grows 0.015% per
+            # step on fine grids and up to 0.5% on coarse ones (von Neumann), too much
+            # for runs of up to 1e5 steps
+            p = k22(n, dx, 0.1 * dx ** 3, 5.0, -60.0, prec=prec)
+            phi0 = k22_compacton(p.grid(), 0.0, float(g.uniform(0.5, 1.5)), float(g.uniform(-40.0, 40.0)),
+                                 period=L)
+    else:
+        # tau = 3: at tau = 1.5 the grid-scale mode grows ~0.1-0.6% per step
+        p = random_m6_problem(g, n)
+        p = dataclasses.replace(p, prec=prec, tau=3.0)
+        x = p.grid() / (n * p.dx)
+        phi0 = 0.3 * np.sin(2 * np.pi * x) + 0.1 * np.cos(6 * np.pi * x + float(g.uniform(0, 6)))
+    return Instance(p, np.ascontiguousarray(phi0, dtype=np.float64), steps)

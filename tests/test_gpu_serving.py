@@ -1,0 +1,126 @@
+"""Serving: continuous batching through lbm_server_* on the GPU.
+
+Each request's result must be the same alone and in the mix (bitwise: every
+kernel path evaluates the same per-node update and a step block boundary only
+stores the state), admission must respect the memory budget, and sampled
+results must match the CPU oracle within the stated tolerances.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lbm_oracle as O
+from paper_0907_1720_amd import lbm, serving
+from paper_0907_1720_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    lbm.library()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _requests(count, n_max=1200, steps_max=2500, start=0):
+    return [W.serving_request(i, n_max=n_max, steps_min=200, steps_max=steps_max) for i in range(start, start + count)]
+
+
+def _state_bytes(p):
+    es = 8 if p.prec == W.F64 else 4
+    return p.lattice() * ((p.n + 63) // 64 * 64) * es
+
+
+def _alone(r):
+    s = lbm.Solver(r.problem)
+    s.load_phi(r.phi0)
+    s.advance(r.steps)
+    out = s.read_phi(allow_nonfinite=True)
+    s.close()
+    return out
+
+
+def test_results_same_alone_and_in_mix_under_small_budget():
+    reqs = _requests(24)
+    budget = 3 * max(_state_bytes(r.problem) for r in reqs)   # forces queueing
+    say("case serving mix", len(reqs), "budget", budget)
+    srv = lbm.Server(budget, max_slots=16, max_n=2048, block_steps=300)
+    ids = [srv.submit(r.problem, r.phi0, r.steps) for r in reqs]
+    got = {}
+    saw_queue = False
+    rounds = 0
+    while len(got) < len(ids):
+        active, queued, retired = srv.step()
+        saw_queue |= queued > 0
+        rounds += 1
+        assert rounds < 10000
+        for k, rid in enumerate(ids):
+            if k in got:
+                continue
+            res = srv.poll(rid)
+            if res is not None:
+                got[k] = res
+    assert saw_queue
+    nu, ms, free = srv.stats()
+    assert free >= budget - 256
+    assert nu == sum(r.problem.n * r.steps for r in reqs)
+    for k, r in enumerate(reqs):
+        phi, st = got[k]
+        assert st == lbm.OK, (k, r.problem.name)
+        assert np.array_equal(phi, _alone(r)), (k, r.problem.name, r.problem.n)
+    srv.close()
+
+
+def test_served_results_match_oracle():
+    reqs = _requests(14, n_max=600, steps_max=1500, start=100)
+    srv = lbm.Server(64 << 20, max_slots=64, max_n=2048, block_steps=400)
+    out = serving.run_poisson(srv, reqs, rate=1e6, keep_results=True)
+    srv.close()
+    assert out["nonfinite"] == 0
+    checked = set()
+    for k, r in enumerate(reqs):
+        if (r.problem.name, r.problem.prec) in checked:
+            continue
+        checked.add((r.problem.name, r.problem.prec))
+        want = O.run(dataclasses.replace(r.problem, prec=W.F64), r.phi0, r.steps)
+        tol = 1e-12 if r.problem.prec == W.F64 else (1e-3 if r.problem.name == "ks" else 1e-4)
+        err = rel2(out["results"][k], want)
+        say("  ", r.problem.name, r.problem.prec, r.problem.n, r.steps, f"{err:.2e}")
+        assert err <= tol, (k, r.problem.name, err)
+
+
+def test_server_refuses_request_larger_than_budget():
+    srv = lbm.Server(1 << 16, max_slots=4, max_n=16384, block_steps=100)
+    p = W.kdv(1.0, 4000, 0.01, 1e-6, 2.0, 0.0)
+    with pytest.raises(lbm.LBMError) as e:
+        srv.submit(p, np.zeros(4000), 10)
+    assert e.value.status == lbm.OUT_OF_MEMORY
+    with pytest.raises(lbm.LBMError) as e:
+        srv.submit(dataclasses.replace(p, n=20000), np.zeros(20000), 10)
+    assert e.value.status == lbm.INVALID_ARG
+    srv.close()
+
+
+def test_poisson_arrivals_report_latency():
+    reqs = _requests(20, n_max=800, steps_max=1000, start=300)
+    srv = lbm.Server(32 << 20, max_slots=8, max_n=1024, block_steps=250)
+    out = serving.run_poisson(srv, reqs, rate=200.0)
+    srv.close()
+    say("  serving", {k: v for k, v in out.items() if k != "results"})
+    assert out["nonfinite"] == 0
+    assert 0.0 < out["p50_latency_s"] <= out["p99_latency_s"]
+    assert out["node_updates"] == sum(r.problem.n * r.steps for r in reqs)
