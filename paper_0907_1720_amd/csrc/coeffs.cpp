@@ -309,6 +309,7 @@ void set_rest_state(Model* mdl, double phi_rest) {
       if (p == 0) {
         mdl->f_rest[j] = (double)h;
         mdl->wfrest[j] = (double)(omega * h);
+        mdl->wG0rest[j] = (double)(omega * (mdl->Gq[j][0] - h));
         mdl->H[j][0] = 0.0;
         mdl->wH[j][0] = 0.0;
       } else {

@@ -31,6 +31,7 @@ struct Model {
   double phi_rest = 0.0;
   double f_rest[kMaxQ] = {};
   double wfrest[kMaxQ] = {};   // omega * f_rest_j
+  double wG0rest[kMaxQ] = {};  // omega * (G[j][0] - f_rest_j), rounded once
   double H[kMaxQ][kMaxDeg + 1] = {};
   double wH[kMaxQ][kMaxDeg + 1] = {};
   // the 113-bit table, kept for the rest-state shift

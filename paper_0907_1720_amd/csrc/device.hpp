@@ -61,11 +61,12 @@ __host__ __device__ constexpr int opposite(int j) {
 // ---- a1 + a2 + a3 + a4: phi = sum_j f_j, f_eq_j(phi) by Horner, BGK ----
 //
 // Storage type T, arithmetic type A; the zeroth moment is always summed in
-// FP64.  Three precisions share this function:
+// FP64.  Three precisions share this code:
 //  * FP64 storage:  f*_j = w0 f_j + sum_d (omega G[j][d]) phi^d
-//  * FP32 deviations g = f - f_rest, FP64 relaxation (REST):
+//  * FP32 deviations g = f - f_rest, FP64 relaxation (kRest):
 //        phi = phi_rest + sum_j g_j,
 //        g*_j = w0 g_j + sum_d (omega G[j][d]) phi^d - omega f_rest_j
+//    (for dense tables the constant -omega f_rest_j is folded into degree 0)
 //  * FP32 deviations, FP32 relaxation: delta = sum_j g_j,
 //        g*_j = w0 g_j + sum_d (omega H[j][d]) delta^d  with H the Taylor shift
 //        of G to the rest state (H[j][0] = 0)
@@ -91,47 +92,79 @@ __device__ __forceinline__ A poly_eval(const A* __restrict__ c, A p) {
   }
 }
 
-template <int Q, int D, int P, typename T, typename A, bool REST>
-__device__ __forceinline__ void collide(T (&f)[Q], const A* __restrict__ wc, A w0, double s0,
-                                        const double* __restrict__ cst) {
-  double s = (double)f[0];
-  if constexpr (REST) s = s0 + s;
+// Per-thread relaxation constants.  The leading coefficient of each
+// polynomial is pinned to a VGPR so that every Horner step is a single FMA
+// with at most one scalar operand.
+template <int Q, int D, int P, typename T, typename A>
+struct Relaxer {
+  static constexpr int K = P == 0 ? D + 1 : (D + 1) / 2;   // coefficients per population
+  static constexpr bool kRest = (sizeof(T) == 4 && sizeof(A) == 8);
+  const A* __restrict__ c;   // [Q][kRow]: dense, or the odd degrees compacted
+  A top[Q];
+  A w0;
+  double s0;
+  const double* __restrict__ cst;
+
+  __device__ __forceinline__ void init(const A* __restrict__ coef, A w0_, const DevCoef* __restrict__ cf) {
+    c = coef;
+    w0 = w0_;
+    s0 = cf->s0;
+    cst = cf->cst;
 #pragma unroll
-  for (int j = 1; j < Q; ++j) s += (double)f[j];
-  const A p = (A)s;
-#pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    const A acc = poly_eval<D, P, A>(wc + j * kRow, p);
-    if constexpr (REST)
-      f[j] = (T)(fma_a(w0, (A)f[j], acc) + cst[j]);
-    else
-      f[j] = (T)fma_a(w0, (A)f[j], acc);
+    for (int j = 0; j < Q; ++j) {
+      top[j] = c[j * kRow + K - 1];
+      asm volatile("" : "+v"(top[j]));
+    }
   }
-}
+
+  __device__ __forceinline__ void operator()(T (&f)[Q]) const {
+    double s = (double)f[0];
+    if constexpr (kRest) s = s0 + s;
+#pragma unroll
+    for (int j = 1; j < Q; ++j) s += (double)f[j];
+    const A p = (A)s;
+    if constexpr (P == 0) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        A acc = top[j];
+#pragma unroll
+        for (int d = K - 2; d >= 0; --d) acc = fma_a(acc, p, c[j * kRow + d]);
+        f[j] = (T)fma_a(w0, (A)f[j], acc);
+      }
+    } else {
+      const A u = p * p;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        A acc = top[j];
+#pragma unroll
+        for (int k = K - 2; k >= 0; --k) acc = fma_a(acc, u, c[j * kRow + k]);
+        acc = fma_a(acc, p, kRest ? (A)cst[j] : (A)0);
+        f[j] = (T)fma_a(w0, (A)f[j], acc);
+      }
+    }
+  }
+};
 
 // Coefficient views by (storage, arithmetic)
 template <typename T, typename A> struct Relax;
 template <> struct Relax<double, double> {
-  static constexpr bool kRest = false;
   __device__ static const double* coef(const DevCoef* c) { return &c->wc[0][0]; }
   __device__ static double w0(const DevCoef* c) { return c->w0; }
 };
 template <> struct Relax<float, double> {
-  static constexpr bool kRest = true;
   __device__ static const double* coef(const DevCoef* c) { return &c->wc[0][0]; }
   __device__ static double w0(const DevCoef* c) { return c->w0; }
 };
 template <> struct Relax<float, float> {
-  static constexpr bool kRest = false;
   __device__ static const float* coef(const DevCoef* c) { return &c->wHf[0][0]; }
   __device__ static float w0(const DevCoef* c) { return c->w0f; }
 };
 
-// one node update, the form every kernel calls
 template <int Q, int D, int P, typename T, typename A>
-__device__ __forceinline__ void collide_node(T (&f)[Q], const A* __restrict__ wc, A w0,
-                                             const DevCoef* __restrict__ cf) {
-  collide<Q, D, P, T, A, Relax<T, A>::kRest>(f, wc, w0, cf->s0, cf->cst);
+__device__ __forceinline__ Relaxer<Q, D, P, T, A> make_relaxer(const DevCoef* __restrict__ cf) {
+  Relaxer<Q, D, P, T, A> r;
+  r.init(Relax<T, A>::coef(cf), Relax<T, A>::w0(cf), cf);
+  return r;
 }
 
 }  // namespace lbm

@@ -38,7 +38,8 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ fin, T* __
   T f[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) f[j] = fin[(int64_t)j * stride + x];
-  collide_node<Q, D, P, T, A>(f, Relax<T, A>::coef(cf), Relax<T, A>::w0(cf), cf);
+  const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
+  relax(f);
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
     int y = x + velocity(j);
@@ -49,12 +50,17 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ fin, T* __
 }
 
 // ---------------------------------------------------------------------------
-// LDS-resident steps of one instance (AA pattern).
-//   even step: node x reads S[j][x], writes f*_j to S[opp(j)][x]
-//   odd step:  node x reads S[opp(j)][x - e_j], writes f*_j to S[j][x + e_j]
+// In-LDS time steps with the alternating (AA) access pattern.  LDS holds node
+// x's populations together (S[x Q + j]; odd Q keeps lane strides free of bank
+// conflicts and every population of a node is an immediate offset from one
+// address).
+//   even step: node x reads S[x][j], writes f*_j to S[x][opp(j)]
+//   odd step:  node x reads S[x - e_j][opp(j)], writes f*_j to S[x + e_j][j]
 // Each node reads exactly the slots it writes, so one barrier per step
 // suffices.  After an even number of steps S is in natural layout
-// (S[j][x] = f_j(x)); after an odd number f_j(x) = S[opp(j)][x - e_j].
+// (S[x][j] = f_j(x)); after an odd number f_j(x) = S[x - e_j][opp(j)].
+// Nodes are updated two at a time (all loads, both relaxations, all stores)
+// so that LDS latency overlaps arithmetic.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wrapn(int y, int n) {
   y += (y < 0) ? n : 0;
@@ -62,49 +68,115 @@ __device__ __forceinline__ int wrapn(int y, int n) {
   return y;
 }
 
+template <int Q, typename T, typename R>
+__device__ __forceinline__ void aa_even(T* __restrict__ S, int x, const R& r) {
+  T* p = S + x * Q;
+  T f[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) f[j] = p[j];
+  r(f);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) p[opposite(j)] = f[j];
+}
+
+template <int Q, typename T, typename R>
+__device__ __forceinline__ void aa_even2(T* __restrict__ S, int x, int y, const R& r) {
+  T* p = S + x * Q;
+  T* q = S + y * Q;
+  T f[Q], h[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    f[j] = p[j];
+    h[j] = q[j];
+  }
+  r(f);
+  r(h);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    p[opposite(j)] = f[j];
+    q[opposite(j)] = h[j];
+  }
+}
+
+template <int Q, typename T, typename R>
+__device__ __forceinline__ void aa_odd(T* __restrict__ S, int x, const R& r) {
+  constexpr int H = Q / 2;
+  T* p = S + (x - H) * Q;
+  T f[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) f[j] = p[(H - velocity(j)) * Q + opposite(j)];
+  r(f);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) p[(H + velocity(j)) * Q + j] = f[j];
+}
+
+template <int Q, typename T, typename R>
+__device__ __forceinline__ void aa_odd2(T* __restrict__ S, int x, int y, const R& r) {
+  constexpr int H = Q / 2;
+  T* p = S + (x - H) * Q;
+  T* q = S + (y - H) * Q;
+  T f[Q], h[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    f[j] = p[(H - velocity(j)) * Q + opposite(j)];
+    h[j] = q[(H - velocity(j)) * Q + opposite(j)];
+  }
+  r(f);
+  r(h);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    p[(H + velocity(j)) * Q + j] = f[j];
+    q[(H + velocity(j)) * Q + j] = h[j];
+  }
+}
+
+// odd step of a node next to the periodic seam
+template <int Q, typename T, typename R>
+__device__ __forceinline__ void aa_odd_wrap(T* __restrict__ S, int x, int n, const R& r) {
+  T f[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) f[j] = S[wrapn(x - velocity(j), n) * Q + opposite(j)];
+  r(f);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) S[wrapn(x + velocity(j), n) * Q + j] = f[j];
+}
+
+// every node x = lo + t + k B below hi, two per iteration
+template <int Q, bool ODD, typename T, typename R>
+__device__ __forceinline__ void aa_sweep(T* __restrict__ S, int lo, int hi, int t, int B, const R& r) {
+  int x = lo + t;
+  for (; x + B < hi; x += 2 * B) {
+    if constexpr (ODD)
+      aa_odd2<Q>(S, x, x + B, r);
+    else
+      aa_even2<Q>(S, x, x + B, r);
+  }
+  if (x < hi) {
+    if constexpr (ODD)
+      aa_odd<Q>(S, x, r);
+    else
+      aa_even<Q>(S, x, r);
+  }
+}
+
 template <int Q, int D, int P, typename T, typename A>
 __device__ void resident_instance(T* __restrict__ S, T* __restrict__ g, int n, int stride, int steps,
                                   const DevCoef* __restrict__ cf, int* __restrict__ status) {
   const int B = blockDim.x;
   const int t = threadIdx.x;
-  const A* __restrict__ wg = Relax<T, A>::coef(cf);
-  const A w0 = Relax<T, A>::w0(cf);
+  const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
   constexpr int H = Q / 2;   // largest |e_j|
 
   for (int j = 0; j < Q; ++j)
-    for (int x = t; x < n; x += B) S[j * n + x] = g[(int64_t)j * stride + x];
+    for (int x = t; x < n; x += B) S[x * Q + j] = g[(int64_t)j * stride + x];
   __syncthreads();
 
   for (int s = 0; s < steps; ++s) {
     if ((s & 1) == 0) {
-      for (int x = t; x < n; x += B) {
-        T f[Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) f[j] = S[j * n + x];
-        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
-#pragma unroll
-        for (int j = 0; j < Q; ++j) S[opposite(j) * n + x] = f[j];
-      }
+      aa_sweep<Q, false>(S, 0, n, t, B, relax);
     } else {
-      // interior nodes: no wrap
-      for (int x = H + t; x < n - H; x += B) {
-        T f[Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * n + x - velocity(j)];
-        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
-#pragma unroll
-        for (int j = 0; j < Q; ++j) S[j * n + x + velocity(j)] = f[j];
-      }
-      // the 2H nodes next to the periodic seam, one per thread
-      if (t < 2 * H) {
-        const int x = t < H ? t : n - 2 * H + t;
-        T f[Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * n + wrapn(x - velocity(j), n)];
-        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
-#pragma unroll
-        for (int j = 0; j < Q; ++j) S[j * n + wrapn(x + velocity(j), n)] = f[j];
-      }
+      aa_sweep<Q, true>(S, H, n - H, t, B, relax);   // interior: no wrap
+      if (t < 2 * H) aa_odd_wrap<Q>(S, t < H ? t : n - 2 * H + t, n, relax);
     }
     __syncthreads();
   }
@@ -114,7 +186,7 @@ __device__ void resident_instance(T* __restrict__ S, T* __restrict__ g, int n, i
   const bool odd = (steps & 1) != 0;
   for (int j = 0; j < Q; ++j) {
     for (int x = t; x < n; x += B) {
-      const T v = odd ? S[opposite(j) * n + wrapn(x - velocity(j), n)] : S[j * n + x];
+      const T v = odd ? S[wrapn(x - velocity(j), n) * Q + opposite(j)] : S[x * Q + j];
       bad |= !__builtin_isfinite(v);
       g[(int64_t)j * stride + x] = v;
     }
@@ -129,7 +201,7 @@ __device__ void resident_instance(T* __restrict__ S, T* __restrict__ g, int n, i
 // fill all 160 KiB: the queue slot is handed to the workgroup through a
 // per-workgroup word in global memory.
 template <int Q, typename T, typename A>
-__global__ __launch_bounds__(256) void k_resident(const DevInst* __restrict__ items, int count,
+__global__ __launch_bounds__(1024) void k_resident(const DevInst* __restrict__ items, int count,
                                                   int* __restrict__ counter, int* __restrict__ slots,
                                                   T* __restrict__ state, const DevCoef* __restrict__ coefs,
                                                   int* __restrict__ status) {
@@ -180,41 +252,25 @@ __device__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* _
                               const DevCoef* __restrict__ cf, int* __restrict__ status) {
   const int B = blockDim.x;
   const int t = threadIdx.x;
-  const A* __restrict__ wg = Relax<T, A>::coef(cf);
-  const A w0 = Relax<T, A>::w0(cf);
+  const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
   constexpr int H = Q / 2;
   const int W = core + 2 * halo;
   for (int j = 0; j < Q; ++j)
-    for (int i = t; i < W; i += B) S[j * W + i] = gin[(int64_t)j * stride + wrap_any(x0 - halo + i, n)];
+    for (int i = t; i < W; i += B) S[i * Q + j] = gin[(int64_t)j * stride + wrap_any(x0 - halo + i, n)];
   __syncthreads();
   for (int s = 0; s < steps; ++s) {
     const int lo = s * H, hi = W - s * H;
-    if ((s & 1) == 0) {
-      for (int x = lo + t; x < hi; x += B) {
-        T f[Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) f[j] = S[j * W + x];
-        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
-#pragma unroll
-        for (int j = 0; j < Q; ++j) S[opposite(j) * W + x] = f[j];
-      }
-    } else {
-      for (int x = lo + t; x < hi; x += B) {
-        T f[Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j) f[j] = S[opposite(j) * W + x - velocity(j)];
-        collide_node<Q, D, P, T, A>(f, wg, w0, cf);
-#pragma unroll
-        for (int j = 0; j < Q; ++j) S[j * W + x + velocity(j)] = f[j];
-      }
-    }
+    if ((s & 1) == 0)
+      aa_sweep<Q, false>(S, lo, hi, t, B, relax);
+    else
+      aa_sweep<Q, true>(S, lo, hi, t, B, relax);
     __syncthreads();
   }
   bool bad = false;
   const bool odd = (steps & 1) != 0;
   for (int j = 0; j < Q; ++j) {
     for (int i = halo + t; i < halo + core; i += B) {
-      const T v = odd ? S[opposite(j) * W + i - velocity(j)] : S[j * W + i];
+      const T v = odd ? S[(i - velocity(j)) * Q + opposite(j)] : S[i * Q + j];
       bad |= !__builtin_isfinite(v);
       gout[(int64_t)j * stride + x0 + (i - halo)] = v;
     }
@@ -225,7 +281,7 @@ __device__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* _
 // One launch = `launch`-th block of up to s steps for every tile.  Instance
 // inputs alternate between the two state buffers from launch to launch.
 template <int Q, typename T, typename A>
-__global__ __launch_bounds__(256) void k_tile(const DevTile* __restrict__ tiles, const DevTileInst* __restrict__ tinsts,
+__global__ __launch_bounds__(1024) void k_tile(const DevTile* __restrict__ tiles, const DevTileInst* __restrict__ tinsts,
                                               T* __restrict__ buf0, T* __restrict__ buf1, int launch, int s_per,
                                               int halo, const DevCoef* __restrict__ coefs,
                                               int* __restrict__ status) {

@@ -135,7 +135,11 @@ void fill_devcoef(const HostInst& h, DevCoef* c) {
     }
     if (h.prec == LBM_F32_DEV) {
       c->s0 = m.phi_rest;
-      for (int j = 0; j < m.q; ++j) c->cst[j] = -m.wfrest[j];
+      for (int j = 0; j < m.q; ++j) {
+        c->cst[j] = -m.wfrest[j];
+        // dense tables absorb the rest-state constant into the degree-0 coefficient
+        if (parity == 0) c->wc[j][0] = m.wG0rest[j];
+      }
     }
   } else {
     for (int j = 0; j < m.q; ++j)
@@ -443,7 +447,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     }
   }
   // temporal blocking plan per (q, prec) group
-  struct TileGroup { int q; int prec; int first, ntiles, tfirst, tcount, s, halo, launches; size_t lds; };
+  struct TileGroup { int q; int prec; int first, ntiles, tfirst, tcount, s, halo, launches, block; size_t lds; };
   std::vector<TileGroup> tgroups;
   std::vector<DevTile> tvec;
   DevTileInst* htin = b->tinsts_host + (size_t)k * count;
@@ -466,7 +470,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       while (sp > 1 && (W - 2 * sp * H < 2 * sp * H || (b->tile_steps == 0 && 8 * sp * H > want))) sp /= 2;
       const int halo = sp * H;
       const int core = std::max(1, std::min(W - 2 * halo, want));
-      TileGroup G{q, pr, (int)tvec.size(), 0, tin_used, 0, sp, halo, 0, 0};
+      TileGroup G{q, pr, (int)tvec.size(), 0, tin_used, 0, sp, halo, 0, kBlock, 0};
       int64_t maxsteps = 0;
       int maxcore = 1;
       for (int i : g) {
@@ -492,6 +496,8 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       G.tcount = tin_used - G.tfirst;
       G.launches = (int)((maxsteps + sp - 1) / sp);
       G.lds = (size_t)q * (maxcore + 2 * halo) * es;
+      // two or more nodes per thread
+      G.block = std::min(kBlock, std::max(64, ((maxcore + 2 * halo) / 2 + 63) / 64 * 64));
       tgroups.push_back(G);
     }
   }
@@ -545,14 +551,21 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const Launch& L = launches[l];
       hipStream_t st = lane_stream(lane);
       if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
+      // workgroup size: about 16 waves per CU across the workgroups the LDS
+      // allows, and at least two nodes per thread
+      int maxn = 0;
+      for (int it = L.first; it < L.first + L.count; ++it) maxn = std::max(maxn, hitems[it].n);
+      const int w = std::max<int>(1, (int)(b->lim.lds_max / std::max<size_t>(L.lds, 1)));
+      int block = std::min(1024, std::max(64, 64 * ((16 + w - 1) / w)));
+      block = std::min(block, std::max(64, (maxn / 2 + 63) / 64 * 64));
       int per_cu = 0;
-      LBM_HIP(resident_occupancy(L.q, L.prec, kBlock, L.lds, &per_cu));
+      LBM_HIP(resident_occupancy(L.q, L.prec, block, L.lds, &per_cu));
       if (per_cu < 1) return LBM_ERR_UNSUPPORTED;
       const int grid = std::min<int>(std::min<int>(L.count, per_cu * b->lim.cus), kMaxResidentGrid);
       void* base = L.prec ? (void*)b->f32[0] : (void*)b->f64[0];
       int* slots = b->slots + (size_t)(k * kMaxLaunches + l) * kMaxResidentGrid;
       LBM_HIP(launch_resident(L.q, L.prec, ditems + L.first, L.count, counters + l, slots, base, b->coefs,
-                              b->status, grid, kBlock, L.lds, st));
+                              b->status, grid, block, L.lds, st));
     }
   }
   for (const TileGroup& G : tgroups) {
@@ -564,7 +577,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     void* b0 = G.prec ? (void*)b->f32[0] : (void*)b->f64[0];
     void* b1 = G.prec ? (void*)b->f32[1] : (void*)b->f64[1];
     for (int l = 0; l < G.launches; ++l)
-      LBM_HIP(launch_tile(G.q, G.prec, dt, G.ntiles, dti, b0, b1, l, G.s, G.halo, b->coefs, b->status, kBlock, G.lds,
+      LBM_HIP(launch_tile(G.q, G.prec, dt, G.ntiles, dti, b0, b1, l, G.s, G.halo, b->coefs, b->status, G.block, G.lds,
                           st));
     for (int t = G.tfirst; t < G.tfirst + G.tcount; ++t) {
       HostInst& h = b->inst[htin[t].inst];
