@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=256.0)
     ap.add_argument("--serve-block", type=int, default=1000)
     ap.add_argument("--serve-budget-gb", type=int, default=16)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="copy 1 GiB device to device first (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the instances are independent, so several GPUs would each "
@@ -99,6 +101,12 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def build_batch(prec):
         insts = [W.config2_instance(i, prec=prec, steps=LB_STEPS) for i in range(args.count)]

@@ -22,15 +22,25 @@ struct DevCoef {
   float wHf[8][kRow];        // FP32 relaxation: omega * H[j][d], H = G shifted to the rest state
 };
 
-// Per-instance launch record of the batched kernels.
-struct DevInst {
+// Resident path: a job is the set of instances one workgroup advances side by
+// side (same step count); each instance owns a wave-aligned range of the
+// workgroup's threads and a region of its LDS.
+struct DevJob {
+  int32_t first;             // first DevJobInst of the job
+  int32_t count;             // instances in the job (<= 16)
+  int32_t steps;             // steps of this launch
+  int32_t degree;            // kernel variant shared by all instances of the job
+};
+struct DevJobInst {
   uint64_t addr;             // device address of row 0 of the instance's current state
   int32_t n;                 // nodes
   int32_t stride;            // row stride in elements
-  int32_t steps;             // steps to run in this launch
   int32_t degree;            // kernel variant: padded degree D | (parity << 8)
-  int32_t q;
   int32_t inst;              // index into coefficients / status
+  int32_t lds_off;           // element offset of the instance's LDS region
+  int32_t t0;                // first thread (multiple of 64)
+  int32_t nt;                // threads (multiple of 64)
+  int32_t pad_;
 };
 
 // Tiled path: one record per tile (workgroup) and one per instance.

@@ -4,9 +4,12 @@
 //  k_init      f := f_eq(phi)                        (initial distribution)
 //  k_stream    one fused collide+stream step, state in HBM, SoA rows,
 //              coalesced loads, shifted stores with periodic wrap
-//  k_resident  persistent work-queue kernel: one workgroup per instance keeps
-//              f in LDS for all steps of the launch; streaming in place with
-//              the alternating (AA) access pattern, one barrier per step
+//  k_resident  persistent work-queue kernel over jobs (instances bin-packed
+//              into a workgroup's LDS, threads split in proportion to their
+//              nodes); f stays in LDS for all steps of the launch; streaming in
+//              place with the alternating (AA) access pattern, one barrier per
+//              step
+//  k_tile      temporal blocking for grids larger than one workgroup's LDS
 //  k_phi       phi = sum_j f_j  (FP64)
 //  k_sum       FP64 sum of phi over a grid, deterministic two-pass
 #include "kernels.hpp"
@@ -159,78 +162,96 @@ __device__ __forceinline__ void aa_sweep(T* __restrict__ S, int lo, int hi, int 
   }
 }
 
+// One job of the resident kernel: every instance of the job (same variant,
+// same step count) is loaded into its LDS region, advanced by its own threads
+// between workgroup barriers, and written back.  Threads beyond the job's
+// instances (mine < 0) only take part in the barriers.
 template <int Q, int D, int P, typename T, typename A>
-__device__ void resident_instance(T* __restrict__ S, T* __restrict__ g, int n, int stride, int steps,
-                                  const DevCoef* __restrict__ cf, int* __restrict__ status) {
-  const int B = blockDim.x;
-  const int t = threadIdx.x;
-  const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
+__device__ void resident_job(T* __restrict__ L, const DevJob& jb, const DevJobInst& ji, int mine, int tid,
+                             const DevCoef* __restrict__ coefs, int* __restrict__ status) {
   constexpr int H = Q / 2;   // largest |e_j|
-
-  for (int j = 0; j < Q; ++j)
-    for (int x = t; x < n; x += B) S[x * Q + j] = g[(int64_t)j * stride + x];
+  const bool act = mine >= 0;
+  T* S = L + ji.lds_off;
+  T* g = reinterpret_cast<T*>(ji.addr);
+  const int t = tid - ji.t0, nt = ji.nt, n = ji.n;
+  const DevCoef* cf = coefs + (act ? ji.inst : 0);
+  const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
+  // interior odd sweeps give threads r..nt-1 one node less, r = (n - 2H) mod nt
+  const int r = (n - 2 * H) % nt;
+  const int seam0 = (r > 0 && r + 2 * H <= nt) ? r : 0;
+  if (act)
+    for (int j = 0; j < Q; ++j)
+      for (int x = t; x < n; x += nt) S[x * Q + j] = g[(int64_t)j * ji.stride + x];
   __syncthreads();
-
-  for (int s = 0; s < steps; ++s) {
-    if ((s & 1) == 0) {
-      aa_sweep<Q, false>(S, 0, n, t, B, relax);
-    } else {
-      aa_sweep<Q, true>(S, H, n - H, t, B, relax);   // interior: no wrap
-      if (t < 2 * H) aa_odd_wrap<Q>(S, t < H ? t : n - 2 * H + t, n, relax);
+  for (int s = 0; s < jb.steps; ++s) {
+    if (act) {
+      if ((s & 1) == 0) {
+        aa_sweep<Q, false>(S, 0, n, t, nt, relax);
+      } else {
+        aa_sweep<Q, true>(S, H, n - H, t, nt, relax);   // interior: no wrap
+        // the 2H seam nodes go to threads with one interior node less
+        const int u = t - seam0;
+        if (u >= 0 && u < 2 * H) aa_odd_wrap<Q>(S, u < H ? u : n - 2 * H + u, n, relax);
+      }
     }
     __syncthreads();
   }
-
   // back to HBM in natural layout; flag non-finite values
-  bool bad = false;
-  const bool odd = (steps & 1) != 0;
-  for (int j = 0; j < Q; ++j) {
-    for (int x = t; x < n; x += B) {
-      const T v = odd ? S[wrapn(x - velocity(j), n) * Q + opposite(j)] : S[x * Q + j];
-      bad |= !__builtin_isfinite(v);
-      g[(int64_t)j * stride + x] = v;
+  if (act) {
+    bool bad = false;
+    const bool odd = (jb.steps & 1) != 0;
+    for (int j = 0; j < Q; ++j) {
+      for (int x = t; x < n; x += nt) {
+        const T v = odd ? S[wrapn(x - velocity(j), n) * Q + opposite(j)] : S[x * Q + j];
+        bad |= !__builtin_isfinite(v);
+        g[(int64_t)j * ji.stride + x] = v;
+      }
     }
+    if (bad) atomicOr(status + ji.inst, 1);
   }
-  if (bad) atomicOr(status, 1);
   __syncthreads();
 }
 
-// Persistent kernel: workgroups take instances from a queue (sorted by work,
-// largest first) until it is empty.  Every instance runs all of its steps of
-// this launch inside LDS.  The kernel uses no static LDS, so an instance may
-// fill all 160 KiB: the queue slot is handed to the workgroup through a
-// per-workgroup word in global memory.
+// Persistent kernel over jobs: a workgroup takes the next job from the queue
+// (largest first) until the queue is empty.  The kernel uses no static LDS (an
+// instance may fill all 160 KiB): the queue slot reaches the workgroup through
+// a per-workgroup word in global memory.
 template <int Q, typename T, typename A>
-__global__ __launch_bounds__(1024) void k_resident(const DevInst* __restrict__ items, int count,
-                                                  int* __restrict__ counter, int* __restrict__ slots,
-                                                  T* __restrict__ state, const DevCoef* __restrict__ coefs,
-                                                  int* __restrict__ status) {
+__global__ __launch_bounds__(1024) void k_resident(const DevJob* __restrict__ jobs, const DevJobInst* __restrict__ jinst,
+                                                   int njobs, int* __restrict__ counter, int* __restrict__ slots,
+                                                   const DevCoef* __restrict__ coefs, int* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* L = reinterpret_cast<T*>(smem_raw);
   int* slot = slots + blockIdx.x;
+  const int tid = threadIdx.x;
   for (;;) {
-    if (threadIdx.x == 0)
-      __hip_atomic_store(slot, atomicAdd(counter, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (tid == 0) __hip_atomic_store(slot, atomicAdd(counter, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(
         __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
     __syncthreads();
-    if (item >= count) break;
-    const DevInst it = items[item];
-    T* g = reinterpret_cast<T*>(it.addr);
-    const DevCoef* cf = coefs + it.inst;
-    int* st = status + it.inst;
-    switch (it.degree) {
-#define LBM_CASE(DD, PP)                                                             \
-  case DD | (PP << 8):                                                               \
-    resident_instance<Q, DD, PP, T, A>(L, g, it.n, it.stride, it.steps, cf, st); \
+    if (item >= njobs) break;
+    const DevJob jb = jobs[item];
+    // the instance of this wave (thread ranges are wave aligned)
+    int mine = -1;
+    for (int k = 0; k < jb.count; ++k) {
+      const DevJobInst& c = jinst[jb.first + k];
+      if (tid >= c.t0 && tid < c.t0 + c.nt) mine = k;
+    }
+    mine = __builtin_amdgcn_readfirstlane(mine);
+    DevJobInst ji{};
+    if (mine >= 0) ji = jinst[jb.first + mine];
+    // the variant is uniform over the workgroup: every thread takes the same case
+    switch (jb.degree) {
+#define LBM_CASE(DD, PP)                                                        \
+  case DD | (PP << 8):                                                          \
+    resident_job<Q, DD, PP, T, A>(L, jb, ji, mine, tid, coefs, status); \
     break;
       LBM_VARIANT_CASES
 #undef LBM_CASE
       default:
         break;
     }
-    __syncthreads();
   }
 }
 
@@ -410,15 +431,21 @@ hipError_t launch_stream(int q, int D, int prec, const void* fin, void* fout, in
                 : launch_stream_q<7, float, float>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
 }
 
-hipError_t launch_resident(int q, int prec, const DevInst* items, int count, int* counter, int* slots,
-                           void* state, const DevCoef* coefs, int* status, int grid, int block, size_t lds,
+hipError_t launch_resident(int q, int prec, const DevJob* jobs, const DevJobInst* jinst, int njobs, int* counter,
+                           int* slots, const DevCoef* coefs, int* status, int grid, int block, size_t lds,
                            hipStream_t s) {
   const void* fn = resident_kernel(q, prec);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  void* args[] = {(void*)&items, (void*)&count, (void*)&counter, (void*)&slots, (void*)&state, (void*)&coefs,
+  void* args[] = {(void*)&jobs, (void*)&jinst, (void*)&njobs, (void*)&counter, (void*)&slots, (void*)&coefs,
                   (void*)&status};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, s);
+}
+
+int resident_vgprs(int q, int prec) {
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, resident_kernel(q, prec)) != hipSuccess || a.numRegs <= 0) return 128;
+  return a.numRegs;
 }
 
 size_t resident_static_lds(int q, int prec) {

@@ -49,9 +49,12 @@ hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n
 // `code` = variant_code(D, parity) of the relaxation polynomial
 hipError_t launch_stream(int q, int code, int prec, const void* fin, void* fout, int n, int stride,
                          const DevCoef* cf, hipStream_t s);
-hipError_t launch_resident(int q, int prec, const DevInst* items, int count, int* counter, int* slots,
-                           void* state, const DevCoef* coefs, int* status, int grid, int block, size_t lds,
+// persistent launch over `njobs` jobs (bin-packed instances)
+hipError_t launch_resident(int q, int prec, const DevJob* jobs, const DevJobInst* jinst, int njobs, int* counter,
+                           int* slots, const DevCoef* coefs, int* status, int grid, int block, size_t lds,
                            hipStream_t s);
+// VGPRs per thread of the resident kernel
+int resident_vgprs(int q, int prec);
 // static LDS bytes of the resident kernel (0 by construction)
 size_t resident_static_lds(int q, int prec);
 hipError_t launch_phi(int prec, const void* f, double* phi, int n, int stride, int q, double phi_rest,

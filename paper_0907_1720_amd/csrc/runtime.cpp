@@ -81,8 +81,10 @@ struct lbm_batch_s {
   int* counter = nullptr;             // work queue counters (one per group launch)
   int* slots = nullptr;               // per-workgroup queue slot of the resident kernel
   int counters_cap = 0;
-  DevInst* items = nullptr;           // two slots of items_cap records (alternating calls)
-  DevInst* items_host = nullptr;      // pinned mirror of both slots
+  DevJobInst* items = nullptr;        // two slots of items_cap records (alternating calls)
+  DevJobInst* items_host = nullptr;   // pinned mirror of both slots
+  DevJob* jobs = nullptr;             // two slots of items_cap jobs
+  DevJob* jobs_host = nullptr;
   hipEvent_t items_done[2] = {nullptr, nullptr};
   int items_cap = 0;
   int slot = 0;
@@ -175,6 +177,8 @@ void destroy_batch(lbm_batch_s* b) {
   hipFree(b->slots);
   hipFree(b->items);
   if (b->items_host) hipHostFree(b->items_host);
+  hipFree(b->jobs);
+  if (b->jobs_host) hipHostFree(b->jobs_host);
   for (int k = 0; k < 2; ++k)
     if (b->items_done[k]) hipEventDestroy(b->items_done[k]);
   hipFree(b->scratch);
@@ -278,8 +282,11 @@ lbm_status alloc_tables(lbm_batch_s* b, size_t maxn) {
   if (hipHostMalloc((void**)&b->tinsts_host, sizeof(DevTileInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
     return LBM_ERR_OUT_OF_MEMORY;
   b->items_cap = count;
-  if (hipMalloc(&b->items, sizeof(DevInst) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
-  if (hipHostMalloc((void**)&b->items_host, sizeof(DevInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
+  if (hipMalloc(&b->items, sizeof(DevJobInst) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  if (hipHostMalloc((void**)&b->items_host, sizeof(DevJobInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
+    return LBM_ERR_OUT_OF_MEMORY;
+  if (hipMalloc(&b->jobs, sizeof(DevJob) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  if (hipHostMalloc((void**)&b->jobs_host, sizeof(DevJob) * 2 * count, hipHostMallocDefault) != hipSuccess)
     return LBM_ERR_OUT_OF_MEMORY;
   for (int k = 0; k < 2; ++k) LBM_HIP(hipEventCreateWithFlags(&b->items_done[k], hipEventDisableTiming));
   b->scratch_elems = maxn + 64;
@@ -397,53 +404,111 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   const int k = b->slot;
   b->slot ^= 1;
   LBM_HIP(hipEventSynchronize(b->items_done[k]));
-  DevInst* hitems = b->items_host + (size_t)k * b->items_cap;
-  struct Launch { int q; int prec; int first, count; size_t lds; };
+  DevJobInst* hitems = b->items_host + (size_t)k * b->items_cap;
+  DevJob* hjobs = b->jobs_host + (size_t)k * b->items_cap;
+  struct Launch { int q; int prec; int first, count; size_t lds; int block; };
   std::vector<Launch> launches;
-  int used = 0;
+  int used = 0, njobs = 0;
+  constexpr int kMaxJobInstances = 16;   // instances per job (one wave each at least)
   for (int qq = 0; qq < 2; ++qq) {
     for (int pr = 0; pr < 3; ++pr) {
       std::vector<int> g = res[qq][pr];
       if (g.empty()) continue;
-      // size classes: LDS bytes in (cap/2^(c+1), cap/2^c], c = 0..3, and the rest;
-      // each class is one launch with its own LDS size, so small instances get
-      // more workgroups per CU
-      auto lds_of = [&](int i) { return (size_t)b->inst[i].q * b->inst[i].n * elem_size(b->inst[i]); };
-      auto class_of = [&](int i) {
-        size_t cap = b->lim.lds_max;
-        int c = 0;
-        while (c < 4 && lds_of(i) * 2 <= cap) {
-          cap /= 2;
-          ++c;
+      const size_t es = pr ? sizeof(float) : sizeof(double);
+      const int q = qq ? 7 : 5;
+      auto bytes_of = [&](int i) { return ((size_t)q * b->inst[i].n * es + 15) / 16 * 16; };
+      // jobs: first-fit decreasing bin packing of equal-step instances into a
+      // workgroup's LDS share (half the LDS, or the largest instance)
+      // jobs hold instances of one variant and one step count
+      std::stable_sort(g.begin(), g.end(), [&](int a, int c) {
+        if (steps[a] != steps[c]) return steps[a] > steps[c];
+        if (b->inst[a].D != b->inst[c].D) return b->inst[a].D < b->inst[c].D;
+        return bytes_of(a) > bytes_of(c);
+      });
+      size_t cap = b->lim.lds_max / 2;
+      for (int i : g) cap = std::max(cap, bytes_of(i));
+      // waves per job: the waves a CU can hold at this kernel's register use,
+      // shared by the jobs whose LDS fits on one CU
+      const int vgprs = std::max(1, resident_vgprs(q, pr));
+      const int cu_waves = 4 * std::max(1, std::min(8, 512 / vgprs));
+      const int jobs_per_cu = std::max<int>(1, (int)(b->lim.lds_max / cap));
+      const int kJobWaves = std::max(1, std::min(16, cu_waves / jobs_per_cu));
+      const int kJobInstances = std::min(kMaxJobInstances, kJobWaves);
+      struct Bin { int64_t steps; int variant; size_t bytes; std::vector<int> members; };
+      std::vector<Bin> bins;
+      size_t open_from = 0;   // bins before this index have another step count or variant
+      for (int i : g) {
+        if (!bins.empty() && (bins.back().steps != steps[i] || bins.back().variant != b->inst[i].D))
+          open_from = bins.size();
+        bool placed = false;
+        for (size_t u = open_from; u < bins.size() && !placed; ++u) {
+          Bin& bn = bins[u];
+          if (bn.bytes + bytes_of(i) <= cap && (int)bn.members.size() < kJobInstances) {
+            bn.bytes += bytes_of(i);
+            bn.members.push_back(i);
+            placed = true;
+          }
         }
-        return c;
+        if (!placed) bins.push_back(Bin{steps[i], b->inst[i].D, bytes_of(i), {i}});
+      }
+      // largest work first (longest-processing-time order for the queue)
+      auto work = [&](const Bin& bn) {
+        int64_t w = 0;
+        for (int i : bn.members) w += (int64_t)b->inst[i].n * bn.steps;
+        return w;
       };
-      std::stable_sort(g.begin(), g.end(), [&](int a, int c) { return class_of(a) < class_of(c); });
-      size_t pos = 0;
-      while (pos < g.size()) {
-        const int cls = class_of(g[pos]);
-        Launch L{qq ? 7 : 5, pr, used, 0, 0};
-        while (pos < g.size() && class_of(g[pos]) == cls) {
-          const int i = g[pos++];
+      std::stable_sort(bins.begin(), bins.end(), [&](const Bin& a, const Bin& c) { return work(a) > work(c); });
+      Launch L{q, pr, njobs, 0, 0, 64};
+      for (const Bin& bn : bins) {
+        // waves: one each, then one more at a time to the member with the most
+        // nodes per wave (at most one wave per 128 nodes)
+        const int m = (int)bn.members.size();
+        std::vector<int> wv(m, 1);
+        int total = m;
+        while (total < kJobWaves) {
+          int best = -1;
+          double load = 0.0;
+          for (int u = 0; u < m; ++u) {
+            const int n = b->inst[bn.members[u]].n;
+            if (wv[u] >= (n + 127) / 128) continue;
+            const double l = (double)n / wv[u];
+            if (l > load) {
+              load = l;
+              best = u;
+            }
+          }
+          if (best < 0) break;
+          ++wv[best];
+          ++total;
+        }
+        DevJob& jb = hjobs[njobs++];
+        jb.first = used;
+        jb.count = m;
+        jb.steps = (int)bn.steps;
+        jb.degree = bn.variant;
+        int t0 = 0, off = 0;
+        for (int u = 0; u < m; ++u) {
+          const int i = bn.members[u];
           const HostInst& h = b->inst[i];
-          DevInst& it = hitems[used++];
+          DevJobInst& it = hitems[used++];
           it.addr = (uint64_t)(uintptr_t)state_cur(b, h);
           it.n = h.n;
           it.stride = h.stride;
-          it.steps = (int)steps[i];
           it.degree = h.D;
-          it.q = h.q;
           it.inst = i;
-          L.lds = std::max(L.lds, lds_of(i));
+          it.lds_off = off;
+          it.t0 = t0;
+          it.nt = 64 * wv[u];
+          it.pad_ = 0;
+          t0 += it.nt;
+          off += (int)(bytes_of(i) / es);
         }
-        L.count = used - L.first;
-        // largest work first (longest-processing-time order for the queue)
-        std::stable_sort(hitems + L.first, hitems + used, [](const DevInst& a, const DevInst& c) {
-          return (int64_t)a.n * a.steps > (int64_t)c.n * c.steps;
-        });
-        if ((int)launches.size() >= kMaxLaunches) return LBM_ERR_UNSUPPORTED;
-        launches.push_back(L);
+        L.lds = std::max(L.lds, (size_t)off * es);
+        L.block = std::max(L.block, t0);
       }
+      L.count = njobs - L.first;
+      if ((int)launches.size() >= kMaxLaunches) return LBM_ERR_UNSUPPORTED;
+      launches.push_back(L);
     }
   }
   // temporal blocking plan per (q, prec) group
@@ -533,40 +598,32 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
                            hipMemcpyHostToDevice, b->stream));
     LBM_HIP(hipMemcpyAsync(dti, htin, sizeof(DevTileInst) * tin_used, hipMemcpyHostToDevice, b->stream));
   }
-  DevInst* ditems = b->items + (size_t)k * b->items_cap;
+  DevJobInst* ditems = b->items + (size_t)k * b->items_cap;
+  DevJob* djobs = b->jobs + (size_t)k * b->items_cap;
   int* counters = b->counter + k * kMaxLaunches;
   if (used) {
-    LBM_HIP(hipMemcpyAsync(ditems, hitems, sizeof(DevInst) * used, hipMemcpyHostToDevice, b->stream));
+    LBM_HIP(hipMemcpyAsync(ditems, hitems, sizeof(DevJobInst) * used, hipMemcpyHostToDevice, b->stream));
+    LBM_HIP(hipMemcpyAsync(djobs, hjobs, sizeof(DevJob) * njobs, hipMemcpyHostToDevice, b->stream));
     LBM_HIP(hipMemsetAsync(counters, 0, sizeof(int) * kMaxLaunches, b->stream));
   }
-  // every resident class launch and every tiled group is a lane on an auxiliary
+  // every resident launch and every tiled group is a lane on an auxiliary
   // stream; the fork is recorded after all table uploads above
   const int lanes = (int)launches.size() + (int)tgroups.size();
   const bool fork = lanes > 1;
   if (fork) LBM_HIP(hipEventRecord(b->fork, b->stream));
   int lane = 0;
   auto lane_stream = [&](int l) -> hipStream_t { return fork ? b->aux[l % kAuxStreams] : b->stream; };
-  if (used) {
-    for (size_t l = 0; l < launches.size(); ++l, ++lane) {
-      const Launch& L = launches[l];
-      hipStream_t st = lane_stream(lane);
-      if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
-      // workgroup size: about 16 waves per CU across the workgroups the LDS
-      // allows, and at least two nodes per thread
-      int maxn = 0;
-      for (int it = L.first; it < L.first + L.count; ++it) maxn = std::max(maxn, hitems[it].n);
-      const int w = std::max<int>(1, (int)(b->lim.lds_max / std::max<size_t>(L.lds, 1)));
-      int block = std::min(1024, std::max(64, 64 * ((16 + w - 1) / w)));
-      block = std::min(block, std::max(64, (maxn / 2 + 63) / 64 * 64));
-      int per_cu = 0;
-      LBM_HIP(resident_occupancy(L.q, L.prec, block, L.lds, &per_cu));
-      if (per_cu < 1) return LBM_ERR_UNSUPPORTED;
-      const int grid = std::min<int>(std::min<int>(L.count, per_cu * b->lim.cus), kMaxResidentGrid);
-      void* base = L.prec ? (void*)b->f32[0] : (void*)b->f64[0];
-      int* slots = b->slots + (size_t)(k * kMaxLaunches + l) * kMaxResidentGrid;
-      LBM_HIP(launch_resident(L.q, L.prec, ditems + L.first, L.count, counters + l, slots, base, b->coefs,
-                              b->status, grid, block, L.lds, st));
-    }
+  for (size_t l = 0; l < launches.size(); ++l, ++lane) {
+    const Launch& L = launches[l];
+    hipStream_t st = lane_stream(lane);
+    if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
+    int per_cu = 0;
+    LBM_HIP(resident_occupancy(L.q, L.prec, L.block, L.lds, &per_cu));
+    if (per_cu < 1) return LBM_ERR_UNSUPPORTED;
+    const int grid = std::min<int>(std::min<int>(L.count, per_cu * b->lim.cus), kMaxResidentGrid);
+    int* slots = b->slots + (size_t)(k * kMaxLaunches + l) * kMaxResidentGrid;
+    LBM_HIP(launch_resident(L.q, L.prec, djobs + L.first, ditems, L.count, counters + l, slots, b->coefs, b->status,
+                            grid, L.block, L.lds, st));
   }
   for (const TileGroup& G : tgroups) {
     hipStream_t st = lane_stream(lane);
