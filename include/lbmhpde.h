@@ -184,6 +184,15 @@ lbm_status lbm_batch_set_path(lbm_batch b, int32_t path);
 /* Temporal blocking parameters of a batch (see lbm_set_tiling). */
 lbm_status lbm_batch_set_tiling(lbm_batch b, int32_t steps_per_launch, int32_t wgs_per_cu);
 
+/* Persistent resident launch parameters of a batch.  max_workgroups caps the
+   grid of each resident launch (0 = as many as the GPU holds at once, at most
+   2048); chunks fixes the number of step chunks each job's steps are split
+   into (0 = automatic: 1 when every job gets its own workgroup, otherwise
+   about 16 queue items per workgroup with chunks of >= 256 steps; at most 64).
+   A chunk reloads its job's state from HBM and writes it back, so results do
+   not depend on either value (bitwise).  INVALID_ARG outside those ranges. */
+lbm_status lbm_batch_set_resident(lbm_batch b, int32_t max_workgroups, int32_t chunks);
+
 lbm_status lbm_batch_destroy(lbm_batch b);
 
 /* ---- serving: continuous batching of solve requests -------------------- */

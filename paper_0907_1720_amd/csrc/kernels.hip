@@ -144,17 +144,21 @@ __device__ __forceinline__ void aa_odd_wrap(T* __restrict__ S, int x, int n, con
   for (int j = 0; j < Q; ++j) S[wrapn(x + velocity(j), n) * Q + j] = f[j];
 }
 
-// every node x = lo + t + k B below hi, two per iteration
-template <int Q, bool ODD, typename T, typename R>
+// every node x = lo + t + k B below hi, U (1 or 2) per iteration: two give
+// each thread two independent updates to interleave, one keeps the register
+// count low enough for eight waves per SIMD
+template <int Q, bool ODD, int U, typename T, typename R>
 __device__ __forceinline__ void aa_sweep(T* __restrict__ S, int lo, int hi, int t, int B, const R& r) {
   int x = lo + t;
-  for (; x + B < hi; x += 2 * B) {
-    if constexpr (ODD)
-      aa_odd2<Q>(S, x, x + B, r);
-    else
-      aa_even2<Q>(S, x, x + B, r);
+  if constexpr (U == 2) {
+    for (; x + B < hi; x += 2 * B) {
+      if constexpr (ODD)
+        aa_odd2<Q>(S, x, x + B, r);
+      else
+        aa_even2<Q>(S, x, x + B, r);
+    }
   }
-  if (x < hi) {
+  for (; x < hi; x += B) {
     if constexpr (ODD)
       aa_odd<Q>(S, x, r);
     else
@@ -167,7 +171,7 @@ __device__ __forceinline__ void aa_sweep(T* __restrict__ S, int lo, int hi, int 
 // between workgroup barriers, and written back.  Threads beyond the job's
 // instances (mine < 0) only take part in the barriers.
 template <int Q, int D, int P, typename T, typename A>
-__device__ void resident_job(T* __restrict__ L, const DevJob& jb, const DevJobInst& ji, int mine, int tid,
+__device__ void resident_job(T* __restrict__ L, int steps, const DevJobInst& ji, int mine, int tid,
                              const DevCoef* __restrict__ coefs, int* __restrict__ status) {
   constexpr int H = Q / 2;   // largest |e_j|
   const bool act = mine >= 0;
@@ -183,12 +187,12 @@ __device__ void resident_job(T* __restrict__ L, const DevJob& jb, const DevJobIn
     for (int j = 0; j < Q; ++j)
       for (int x = t; x < n; x += nt) S[x * Q + j] = g[(int64_t)j * ji.stride + x];
   __syncthreads();
-  for (int s = 0; s < jb.steps; ++s) {
+  for (int s = 0; s < steps; ++s) {
     if (act) {
       if ((s & 1) == 0) {
-        aa_sweep<Q, false>(S, 0, n, t, nt, relax);
+        aa_sweep<Q, false, 1>(S, 0, n, t, nt, relax);
       } else {
-        aa_sweep<Q, true>(S, H, n - H, t, nt, relax);   // interior: no wrap
+        aa_sweep<Q, true, 1>(S, H, n - H, t, nt, relax);   // interior: no wrap
         // the 2H seam nodes go to threads with one interior node less
         const int u = t - seam0;
         if (u >= 0 && u < 2 * H) aa_odd_wrap<Q>(S, u < H ? u : n - 2 * H + u, n, relax);
@@ -199,7 +203,7 @@ __device__ void resident_job(T* __restrict__ L, const DevJob& jb, const DevJobIn
   // back to HBM in natural layout; flag non-finite values
   if (act) {
     bool bad = false;
-    const bool odd = (jb.steps & 1) != 0;
+    const bool odd = (steps & 1) != 0;
     for (int j = 0; j < Q; ++j) {
       for (int x = t; x < n; x += nt) {
         const T v = odd ? S[wrapn(x - velocity(j), n) * Q + opposite(j)] : S[x * Q + j];
@@ -212,45 +216,84 @@ __device__ void resident_job(T* __restrict__ L, const DevJob& jb, const DevJobIn
   __syncthreads();
 }
 
-// Persistent kernel over jobs: a workgroup takes the next job from the queue
-// (largest first) until the queue is empty.  The kernel uses no static LDS (an
+// Persistent kernel over jobs: a workgroup takes the next item from the queue
+// until the queue is empty.  Each job's steps are split into `nchunks` chunks
+// (a chunk loads the job's state from HBM, advances it and writes it back), and
+// the queue holds every job's chunk 0 (longest job first), then every chunk 1,
+// and so on, so that the last items of the launch are short and the CUs finish
+// together.  Chunk c of job j starts once chunk c-1 of job j has published its
+// state (done[j] == c); that chunk was taken from the queue earlier by a
+// running workgroup, so every wait ends.  The kernel uses no static LDS (an
 // instance may fill all 160 KiB): the queue slot reaches the workgroup through
-// a per-workgroup word in global memory.
-template <int Q, typename T, typename A>
-__global__ __launch_bounds__(1024) void k_resident(const DevJob* __restrict__ jobs, const DevJobInst* __restrict__ jinst,
-                                                   int njobs, int* __restrict__ counter, int* __restrict__ slots,
+// a per-workgroup word in global memory.  One instantiation per equilibrium
+// variant, so that each runs at its own register count and occupancy: the
+// light variants (one node per iteration fits 64 VGPRs without spilling) are
+// compiled for eight waves per SIMD, the others without a bound.
+template <int Q, int D, int P, typename A>
+constexpr int resident_waves_per_simd() {
+  if constexpr (sizeof(A) == 4) return 8;
+  if constexpr (Q == 5) return (P ? D <= 9 : D <= 5) ? 8 : 1;
+  return 1;
+}
+
+template <int Q, int D, int P, typename T, typename A>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(resident_waves_per_simd<Q, D, P, A>())))
+void k_resident(const DevJob* __restrict__ jobs, const DevJobInst* __restrict__ jinst,
+                                                   int njobs, int nchunks, int* __restrict__ counter,
+                                                   int* __restrict__ slots, int* __restrict__ done,
                                                    const DevCoef* __restrict__ coefs, int* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* L = reinterpret_cast<T*>(smem_raw);
   int* slot = slots + blockIdx.x;
   const int tid = threadIdx.x;
+  // The only thread-0 branch that ends next to the loop's back edge is the one
+  // at the top: it publishes the previous item's chunk and takes the next item.
+  // (A second thread-0 branch at the end of the body can be merged with it
+  // across the back edge, which gives thread 0 a loop exit of its own while the
+  // other threads of its wave go round again.)
+  int pub_job = -1, pub_val = 0;
   for (;;) {
-    if (tid == 0) __hip_atomic_store(slot, atomicAdd(counter, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (tid == 0) {
+      if (pub_job >= 0) __hip_atomic_store(done + pub_job, pub_val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(slot, atomicAdd(counter, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(
         __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
     __syncthreads();
-    if (item >= njobs) break;
-    const DevJob jb = jobs[item];
-    // the instance of this wave (thread ranges are wave aligned)
-    int mine = -1;
-    for (int k = 0; k < jb.count; ++k) {
-      const DevJobInst& c = jinst[jb.first + k];
-      if (tid >= c.t0 && tid < c.t0 + c.nt) mine = k;
-    }
-    mine = __builtin_amdgcn_readfirstlane(mine);
-    DevJobInst ji{};
-    if (mine >= 0) ji = jinst[jb.first + mine];
-    // the variant is uniform over the workgroup: every thread takes the same case
-    switch (jb.degree) {
-#define LBM_CASE(DD, PP)                                                        \
-  case DD | (PP << 8):                                                          \
-    resident_job<Q, DD, PP, T, A>(L, jb, ji, mine, tid, coefs, status); \
-    break;
-      LBM_VARIANT_CASES
-#undef LBM_CASE
-      default:
-        break;
+    if (item >= njobs * nchunks) break;
+    const int c = item / njobs;
+    const int jid = item - c * njobs;
+    const DevJob jb = jobs[jid];
+    // an empty chunk is followed by empty chunks only: nobody waits for it
+    const int steps = jb.steps / nchunks + (c < jb.steps % nchunks ? 1 : 0);
+    pub_job = -1;
+    if (steps > 0) {
+      if (c > 0) {
+        if (tid == 0) {
+          while (__hip_atomic_load(done + jid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < c)
+            __builtin_amdgcn_s_sleep(8);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every wave drops stale cached lines
+      }
+      // the instance of this wave (thread ranges are wave aligned)
+      int mine = -1;
+      for (int k = 0; k < jb.count; ++k) {
+        const DevJobInst& ck = jinst[jb.first + k];
+        if (tid >= ck.t0 && tid < ck.t0 + ck.nt) mine = k;
+      }
+      mine = __builtin_amdgcn_readfirstlane(mine);
+      DevJobInst ji{};
+      if (mine >= 0) ji = jinst[jb.first + mine];
+      resident_job<Q, D, P, T, A>(L, steps, ji, mine, tid, coefs, status);
+      if (c + 1 < nchunks) {
+        __threadfence();   // this thread's write-back is visible to every CU
+        __syncthreads();
+        pub_job = jid;
+        pub_val = c + 1;
+      }
     }
   }
 }
@@ -282,9 +325,9 @@ __device__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* _
   for (int s = 0; s < steps; ++s) {
     const int lo = s * H, hi = W - s * H;
     if ((s & 1) == 0)
-      aa_sweep<Q, false>(S, lo, hi, t, B, relax);
+      aa_sweep<Q, false, 2>(S, lo, hi, t, B, relax);
     else
-      aa_sweep<Q, true>(S, lo, hi, t, B, relax);
+      aa_sweep<Q, true, 2>(S, lo, hi, t, B, relax);
     __syncthreads();
   }
   bool bad = false;
@@ -395,17 +438,26 @@ hipError_t launch_stream_q(int code, const T* fin, T* fout, int n, int stride, c
 }
 
 template <int Q, typename T, typename A>
-const void* resident_fn() { return (const void*)k_resident<Q, T, A>; }
-
-const void* resident_kernel(int q, int prec) {
-  if (q == 5) {
-    if (prec == 0) return resident_fn<5, double, double>();
-    if (prec == 1) return resident_fn<5, float, double>();
-    return resident_fn<5, float, float>();
+const void* resident_fn(int code) {
+  switch (code) {
+#define LBM_CASE(DD, PP) \
+  case DD | (PP << 8):   \
+    return (const void*)k_resident<Q, DD, PP, T, A>;
+    LBM_VARIANT_CASES
+#undef LBM_CASE
   }
-  if (prec == 0) return resident_fn<7, double, double>();
-  if (prec == 1) return resident_fn<7, float, double>();
-  return resident_fn<7, float, float>();
+  return nullptr;
+}
+
+const void* resident_kernel(int q, int prec, int code) {
+  if (q == 5) {
+    if (prec == 0) return resident_fn<5, double, double>(code);
+    if (prec == 1) return resident_fn<5, float, double>(code);
+    return resident_fn<5, float, float>(code);
+  }
+  if (prec == 0) return resident_fn<7, double, double>(code);
+  if (prec == 1) return resident_fn<7, float, double>(code);
+  return resident_fn<7, float, float>(code);
 }
 }  // namespace
 
@@ -431,26 +483,29 @@ hipError_t launch_stream(int q, int D, int prec, const void* fin, void* fout, in
                 : launch_stream_q<7, float, float>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
 }
 
-hipError_t launch_resident(int q, int prec, const DevJob* jobs, const DevJobInst* jinst, int njobs, int* counter,
-                           int* slots, const DevCoef* coefs, int* status, int grid, int block, size_t lds,
-                           hipStream_t s) {
-  const void* fn = resident_kernel(q, prec);
+hipError_t launch_resident(int q, int prec, int code, const DevJob* jobs, const DevJobInst* jinst, int njobs,
+                           int nchunks, int* counter, int* slots, int* done, const DevCoef* coefs, int* status,
+                           int grid, int block, size_t lds, hipStream_t s) {
+  const void* fn = resident_kernel(q, prec, code);
+  if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  void* args[] = {(void*)&jobs, (void*)&jinst, (void*)&njobs, (void*)&counter, (void*)&slots, (void*)&coefs,
-                  (void*)&status};
+  void* args[] = {(void*)&jobs,  (void*)&jinst, (void*)&njobs, (void*)&nchunks, (void*)&counter,
+                  (void*)&slots, (void*)&done,  (void*)&coefs, (void*)&status};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, s);
 }
 
-int resident_vgprs(int q, int prec) {
+int resident_vgprs(int q, int prec, int code) {
   hipFuncAttributes a;
-  if (hipFuncGetAttributes(&a, resident_kernel(q, prec)) != hipSuccess || a.numRegs <= 0) return 128;
+  const void* fn = resident_kernel(q, prec, code);
+  if (!fn || hipFuncGetAttributes(&a, fn) != hipSuccess || a.numRegs <= 0) return 128;
   return a.numRegs;
 }
 
-size_t resident_static_lds(int q, int prec) {
+size_t resident_static_lds(int q, int prec, int code) {
   hipFuncAttributes a;
-  if (hipFuncGetAttributes(&a, resident_kernel(q, prec)) != hipSuccess) return 1024;
+  const void* fn = resident_kernel(q, prec, code);
+  if (!fn || hipFuncGetAttributes(&a, fn) != hipSuccess) return 1024;
   return a.sharedSizeBytes;
 }
 
@@ -480,8 +535,9 @@ hipError_t launch_tile(int q, int prec, const DevTile* tiles, int ntiles, const 
   return hipLaunchKernel(fn, dim3(ntiles), dim3(block), args, lds, s);
 }
 
-hipError_t resident_occupancy(int q, int prec, int block, size_t lds, int* blocks_per_cu) {
-  const void* fn = resident_kernel(q, prec);
+hipError_t resident_occupancy(int q, int prec, int code, int block, size_t lds, int* blocks_per_cu) {
+  const void* fn = resident_kernel(q, prec, code);
+  if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, lds);

@@ -49,18 +49,19 @@ hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n
 // `code` = variant_code(D, parity) of the relaxation polynomial
 hipError_t launch_stream(int q, int code, int prec, const void* fin, void* fout, int n, int stride,
                          const DevCoef* cf, hipStream_t s);
-// persistent launch over `njobs` jobs (bin-packed instances)
-hipError_t launch_resident(int q, int prec, const DevJob* jobs, const DevJobInst* jinst, int njobs, int* counter,
-                           int* slots, const DevCoef* coefs, int* status, int grid, int block, size_t lds,
-                           hipStream_t s);
-// VGPRs per thread of the resident kernel
-int resident_vgprs(int q, int prec);
+// persistent launch over `njobs` jobs (bin-packed instances of one variant
+// `code`), each split into `nchunks` step chunks; done[0..njobs) starts at 0
+hipError_t launch_resident(int q, int prec, int code, const DevJob* jobs, const DevJobInst* jinst, int njobs,
+                           int nchunks, int* counter, int* slots, int* done, const DevCoef* coefs, int* status,
+                           int grid, int block, size_t lds, hipStream_t s);
+// VGPRs per thread of the resident kernel of variant `code`
+int resident_vgprs(int q, int prec, int code);
 // static LDS bytes of the resident kernel (0 by construction)
-size_t resident_static_lds(int q, int prec);
+size_t resident_static_lds(int q, int prec, int code);
 hipError_t launch_phi(int prec, const void* f, double* phi, int n, int stride, int q, double phi_rest,
                       int* nonfinite, hipStream_t s);
 hipError_t launch_sum(const double* v, int n, double* part, int nparts, hipStream_t s);
-hipError_t resident_occupancy(int q, int prec, int block, size_t lds, int* blocks_per_cu);
+hipError_t resident_occupancy(int q, int prec, int code, int block, size_t lds, int* blocks_per_cu);
 // temporal blocking: launch `launch` of an advance, s_per steps per launch
 hipError_t launch_tile(int q, int prec, const DevTile* tiles, int ntiles, const DevTileInst* tinsts, void* buf0,
                        void* buf1, int launch, int s_per, int halo, const DevCoef* coefs, int* status, int block,

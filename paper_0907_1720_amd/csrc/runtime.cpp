@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <new>
 #include <vector>
 
@@ -25,8 +27,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxResidentGrid = 256 * 8;
-constexpr int kMaxLaunches = 32;      // resident launches per advance pass
-constexpr int kAuxStreams = 8;        // concurrent size classes
+constexpr int kMaxLaunches = 64;      // resident launches per advance pass (one per lattice, precision, variant)
+constexpr int kAuxStreams = 8;        // concurrent lanes (resident launches, tiled groups)
 constexpr uint64_t kMagic = 0x4c424d4850444531ull;   // "LBMHPDE1"
 
 struct HostInst {
@@ -84,6 +86,7 @@ struct lbm_batch_s {
   DevJobInst* items = nullptr;        // two slots of items_cap records (alternating calls)
   DevJobInst* items_host = nullptr;   // pinned mirror of both slots
   DevJob* jobs = nullptr;             // two slots of items_cap jobs
+  int* done = nullptr;                // per job: chunks published (two slots of items_cap)
   DevJob* jobs_host = nullptr;
   hipEvent_t items_done[2] = {nullptr, nullptr};
   int items_cap = 0;
@@ -100,6 +103,8 @@ struct lbm_batch_s {
   DevTileInst* tinsts_host = nullptr;
   int tile_steps = 0;                 // steps per tiled launch (0 = automatic)
   int tile_wgs = 0;                   // tiled workgroups per CU the LDS budget is split for (0 = automatic)
+  int res_grid = 0;                   // cap on the resident grid (0 = automatic)
+  int res_chunks = 0;                 // step chunks per resident job (0 = automatic)
   hipStream_t aux[kAuxStreams] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kAuxStreams] = {};
@@ -178,6 +183,7 @@ void destroy_batch(lbm_batch_s* b) {
   hipFree(b->items);
   if (b->items_host) hipHostFree(b->items_host);
   hipFree(b->jobs);
+  hipFree(b->done);
   if (b->jobs_host) hipHostFree(b->jobs_host);
   for (int k = 0; k < 2; ++k)
     if (b->items_done[k]) hipEventDestroy(b->items_done[k]);
@@ -286,6 +292,7 @@ lbm_status alloc_tables(lbm_batch_s* b, size_t maxn) {
   if (hipHostMalloc((void**)&b->items_host, sizeof(DevJobInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
     return LBM_ERR_OUT_OF_MEMORY;
   if (hipMalloc(&b->jobs, sizeof(DevJob) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+  if (hipMalloc(&b->done, sizeof(int) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
   if (hipHostMalloc((void**)&b->jobs_host, sizeof(DevJob) * 2 * count, hipHostMallocDefault) != hipSuccess)
     return LBM_ERR_OUT_OF_MEMORY;
   for (int k = 0; k < 2; ++k) LBM_HIP(hipEventCreateWithFlags(&b->items_done[k], hipEventDisableTiming));
@@ -375,16 +382,19 @@ lbm_status load_phi_one(lbm_batch_s* b, int i, const double* phi, int on_device)
 }
 
 bool fits_resident(const lbm_batch_s* b, const HostInst& h) {
-  return (size_t)h.q * h.n * elem_size(h) + resident_static_lds(h.q, h.prec) <= b->lim.lds_max;
+  return (size_t)h.q * h.n * elem_size(h) + resident_static_lds(h.q, h.prec, h.D) <= b->lim.lds_max;
 }
 
 constexpr int64_t kMaxStepsPerLaunch = int64_t(1) << 30;
+constexpr int kChunkItems = 16;        // queue items per workgroup when jobs outnumber workgroups
+constexpr int64_t kMinChunkSteps = 256;
+constexpr int kMaxChunks = 64;
 
 // One pass: every instance advances by steps[i] <= kMaxStepsPerLaunch.
 lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   const int count = (int)b->inst.size();
-  // resident groups by (q, precision); the rest streams through HBM
-  std::vector<int> res[2][3];   // [q == 7][prec]
+  // resident groups by (q, precision, variant); the rest streams through HBM
+  std::map<std::tuple<int, int, int>, std::vector<int>> res;   // (q == 7, prec, variant code)
   std::vector<int> str;          // one launch per step (the plain path)
   std::vector<int> til[2][3];    // temporal blocking, by (q, prec)
   for (int i = 0; i < count; ++i) {
@@ -397,7 +407,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     else if (b->path == 3 || !fits)
       til[h.q == 7][h.prec].push_back(i);
     else
-      res[h.q == 7][h.prec].push_back(i);
+      res[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D)].push_back(i);
   }
   // item records of this call go to slot `k`; wait until the copy issued from
   // the same slot two calls ago has been consumed
@@ -406,16 +416,16 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   LBM_HIP(hipEventSynchronize(b->items_done[k]));
   DevJobInst* hitems = b->items_host + (size_t)k * b->items_cap;
   DevJob* hjobs = b->jobs_host + (size_t)k * b->items_cap;
-  struct Launch { int q; int prec; int first, count; size_t lds; int block; };
+  struct Launch { int q; int prec; int code; int first, count; size_t lds; int block; int64_t maxsteps; };
   std::vector<Launch> launches;
   int used = 0, njobs = 0;
   constexpr int kMaxJobInstances = 16;   // instances per job (one wave each at least)
-  for (int qq = 0; qq < 2; ++qq) {
-    for (int pr = 0; pr < 3; ++pr) {
-      std::vector<int> g = res[qq][pr];
-      if (g.empty()) continue;
+  for (const auto& group : res) {
+    {
+      const int pr = std::get<1>(group.first), code = std::get<2>(group.first);
+      std::vector<int> g = group.second;
       const size_t es = pr ? sizeof(float) : sizeof(double);
-      const int q = qq ? 7 : 5;
+      const int q = std::get<0>(group.first) ? 7 : 5;
       auto bytes_of = [&](int i) { return ((size_t)q * b->inst[i].n * es + 15) / 16 * 16; };
       // jobs: first-fit decreasing bin packing of equal-step instances into a
       // workgroup's LDS share (half the LDS, or the largest instance)
@@ -429,7 +439,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       for (int i : g) cap = std::max(cap, bytes_of(i));
       // waves per job: the waves a CU can hold at this kernel's register use,
       // shared by the jobs whose LDS fits on one CU
-      const int vgprs = std::max(1, resident_vgprs(q, pr));
+      const int vgprs = std::max(1, resident_vgprs(q, pr, code));
       const int cu_waves = 4 * std::max(1, std::min(8, 512 / vgprs));
       const int jobs_per_cu = std::max<int>(1, (int)(b->lim.lds_max / cap));
       const int kJobWaves = std::max(1, std::min(16, cu_waves / jobs_per_cu));
@@ -451,14 +461,9 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
         }
         if (!placed) bins.push_back(Bin{steps[i], b->inst[i].D, bytes_of(i), {i}});
       }
-      // largest work first (longest-processing-time order for the queue)
-      auto work = [&](const Bin& bn) {
-        int64_t w = 0;
-        for (int i : bn.members) w += (int64_t)b->inst[i].n * bn.steps;
-        return w;
-      };
-      std::stable_sort(bins.begin(), bins.end(), [&](const Bin& a, const Bin& c) { return work(a) > work(c); });
-      Launch L{q, pr, njobs, 0, 0, 64};
+      Launch L{q, pr, code, njobs, 0, 0, 64, 0};
+      struct Planned { const Bin* bin; std::vector<int> waves; double est; };
+      std::vector<Planned> plan;
       for (const Bin& bn : bins) {
         // waves: one each, then one more at a time to the member with the most
         // nodes per wave (at most one wave per 128 nodes)
@@ -481,6 +486,19 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
           ++wv[best];
           ++total;
         }
+        // duration estimate: steps x nodes of the busiest thread x arithmetic per node
+        int npt = 1;
+        for (int u = 0; u < m; ++u) npt = std::max(npt, (b->inst[bn.members[u]].n + 64 * wv[u] - 1) / (64 * wv[u]));
+        const int dd = b->inst[bn.members[0]].D & 0xff;
+        plan.push_back(Planned{&bn, wv, (double)bn.steps * npt * (q * (dd + 3))});
+      }
+      // longest job first (longest-processing-time order for the queue)
+      std::stable_sort(plan.begin(), plan.end(), [](const Planned& a, const Planned& c) { return a.est > c.est; });
+      for (const Planned& pl : plan) {
+        const Bin& bn = *pl.bin;
+        const std::vector<int>& wv = pl.waves;
+        const int m = (int)bn.members.size();
+        L.maxsteps = std::max<int64_t>(L.maxsteps, bn.steps);
         DevJob& jb = hjobs[njobs++];
         jb.first = used;
         jb.count = m;
@@ -605,6 +623,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     LBM_HIP(hipMemcpyAsync(ditems, hitems, sizeof(DevJobInst) * used, hipMemcpyHostToDevice, b->stream));
     LBM_HIP(hipMemcpyAsync(djobs, hjobs, sizeof(DevJob) * njobs, hipMemcpyHostToDevice, b->stream));
     LBM_HIP(hipMemsetAsync(counters, 0, sizeof(int) * kMaxLaunches, b->stream));
+    LBM_HIP(hipMemsetAsync(b->done + (size_t)k * b->items_cap, 0, sizeof(int) * njobs, b->stream));
   }
   // every resident launch and every tiled group is a lane on an auxiliary
   // stream; the fork is recorded after all table uploads above
@@ -618,12 +637,24 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     hipStream_t st = lane_stream(lane);
     if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
     int per_cu = 0;
-    LBM_HIP(resident_occupancy(L.q, L.prec, L.block, L.lds, &per_cu));
+    LBM_HIP(resident_occupancy(L.q, L.prec, L.code, L.block, L.lds, &per_cu));
     if (per_cu < 1) return LBM_ERR_UNSUPPORTED;
-    const int grid = std::min<int>(std::min<int>(L.count, per_cu * b->lim.cus), kMaxResidentGrid);
+    int grid = std::min<int>(std::min<int>(L.count, per_cu * b->lim.cus), kMaxResidentGrid);
+    if (b->res_grid > 0) grid = std::min(grid, b->res_grid);
+    // more jobs than workgroups: split the steps into chunks so that each
+    // workgroup takes about kChunkItems items and the launch ends evenly;
+    // chunks keep at least kMinChunkSteps steps (a chunk reloads its state)
+    int nchunks = 1;
+    if (L.count > grid) {
+      nchunks = (int)std::min<int64_t>((kChunkItems * (int64_t)grid + L.count - 1) / L.count,
+                                       std::max<int64_t>(1, L.maxsteps / kMinChunkSteps));
+      nchunks = std::max(1, std::min(nchunks, kMaxChunks));
+    }
+    if (b->res_chunks > 0) nchunks = b->res_chunks;
     int* slots = b->slots + (size_t)(k * kMaxLaunches + l) * kMaxResidentGrid;
-    LBM_HIP(launch_resident(L.q, L.prec, djobs + L.first, ditems, L.count, counters + l, slots, b->coefs, b->status,
-                            grid, L.block, L.lds, st));
+    int* done = b->done + (size_t)k * b->items_cap + L.first;
+    LBM_HIP(launch_resident(L.q, L.prec, L.code, djobs + L.first, ditems, L.count, nchunks, counters + l, slots, done,
+                            b->coefs, b->status, grid, L.block, L.lds, st));
   }
   for (const TileGroup& G : tgroups) {
     hipStream_t st = lane_stream(lane);
@@ -940,6 +971,14 @@ lbm_status lbm_batch_set_tiling(lbm_batch b, int32_t steps_per_launch, int32_t w
     return LBM_ERR_INVALID_ARG;
   b->tile_steps = steps_per_launch;
   b->tile_wgs = wgs_per_cu;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_resident(lbm_batch b, int32_t max_workgroups, int32_t chunks) {
+  if (!b || max_workgroups < 0 || max_workgroups > kMaxResidentGrid || chunks < 0 || chunks > kMaxChunks)
+    return LBM_ERR_INVALID_ARG;
+  b->res_grid = max_workgroups;
+  b->res_chunks = chunks;
   return LBM_OK;
 }
 

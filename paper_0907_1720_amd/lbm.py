@@ -87,6 +87,7 @@ def library() -> ctypes.CDLL:
         "lbm_batch_last_advance_ms": (I32, [P, P]),
         "lbm_batch_set_path": (I32, [P, I32]),
         "lbm_batch_set_tiling": (I32, [P, I32, I32]),
+        "lbm_batch_set_resident": (I32, [P, I32, I32]),
         "lbm_batch_destroy": (I32, [P]),
         "lbm_server_create": (I32, [P, SZ, I32, I64, I32, P]),
         "lbm_server_submit": (I32, [P, DP, P, I64, P]),
@@ -294,6 +295,10 @@ class Batch:
     def set_tiling(self, steps_per_launch: int = 0, wgs_per_cu: int = 0):
         _check(library().lbm_batch_set_tiling(self._h, int(steps_per_launch), int(wgs_per_cu)),
                "lbm_batch_set_tiling")
+
+    def set_resident(self, max_workgroups: int = 0, chunks: int = 0):
+        _check(library().lbm_batch_set_resident(self._h, int(max_workgroups), int(chunks)),
+               "lbm_batch_set_resident")
 
     def last_advance_ms(self) -> float:
         ms = ctypes.c_float()

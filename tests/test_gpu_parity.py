@@ -222,6 +222,40 @@ def test_batch_instance_alone_equals_in_mix():
     b.close()
 
 
+@pytest.mark.parametrize("prec", [W.F64, W.F32_DEV])
+def test_resident_step_chunks_bitwise(prec):
+    """Splitting each job's steps into chunks (each chunk reloads and writes
+    back its state, chunks of one job wait for each other across workgroups)
+    changes nothing: the per-node update and the state bits are the same."""
+    insts = _config2(prec, 40)
+    steps = [333 + (k % 3) for k in range(len(insts))]   # odd and even chunk lengths
+    res = []
+    for grid, chunks in ((0, 0), (3, 5), (1, 7), (2, 64), (0, 2)):
+        say("case chunks", prec, grid, chunks)
+        b = lbm.Batch([i.problem for i in insts])
+        b.set_path(lbm.PATH_RESIDENT)
+        b.set_resident(grid, chunks)
+        b.load_phi([i.phi0 for i in insts])
+        b.advance(steps)
+        b.advance(10)   # fewer steps than chunks: empty chunks are skipped
+        res.append([b.read_phi(k) for k in range(len(insts))])
+        b.close()
+    for r in res[1:]:
+        for (a, sa), (c, sc) in zip(res[0], r):
+            assert sa == lbm.OK and sc == lbm.OK
+            assert np.array_equal(a, c)
+
+
+def test_resident_parameters_validated():
+    insts = _config2(W.F64, 2)
+    b = lbm.Batch([i.problem for i in insts])
+    for grid, chunks in ((-1, 0), (0, -1), (4096, 0), (0, 65)):
+        with pytest.raises(lbm.LBMError) as e:
+            b.set_resident(grid, chunks)
+        assert e.value.status == lbm.INVALID_ARG
+    b.close()
+
+
 def test_batch_streaming_path_bitwise_equals_resident():
     insts = _config2(W.F64, 6)
     res = []
