@@ -21,10 +21,11 @@ Reported:
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import hashlib
 import json
-import math
 import multiprocessing as mp
 import os
+import re
 import sys
 import time
 
@@ -38,6 +39,31 @@ from paper_0907_1720_amd import workloads as W  # noqa: E402
 COUNT = 4096
 LB_STEPS = 5000
 PEAK_VALU_TFLOPS = 78.6      # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 flop/FMA (FP64 = non-packed FP32)
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_counters_kdv_mkdv_batch4096.md")
+KERNEL_SOURCES = ("kernels.hip", "device.hpp", "kernels.hpp", "runtime.cpp")
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the sources that decide what the resident kernels read and write."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0907_1720_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per FP32 pass from the committed FETCH_SIZE / WRITE_SIZE record,
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_RECORD).read()
+    except OSError:
+        return None
+    dig = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    val = re.search(r"hbm_bytes_per_pass:\s*([0-9.eE+]+)", text)
+    if not dig or not val or dig.group(1) != kernel_source_digest():
+        return None
+    return float(val.group(1))
 
 
 def algorithmic_flops_per_nu(G: np.ndarray) -> int:
@@ -89,6 +115,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device to device first (reference kernel for HBM counters)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the FP32 batch (for profiler runs); prints a reduced line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the instances are independent, so several GPUs would each "
@@ -138,6 +166,11 @@ def main():
                 "nu_per_s": nu_pass * args.steps / wall, "status_ok": all(s == lbm.OK for s in st)}
 
     r32 = run(W.F32_DEV)
+    if args.batch_only:
+        print(json.dumps({"metric": "lattice-node updates/s (FP32 batch only)", "value": r32["nu_per_s"],
+                          "unit": "node-updates/s", "steps": args.steps, "warmup": args.warmup,
+                          "kernel_ms": r32["kernel_ms"], "status_ok": r32["status_ok"]}))
+        return
     r64 = run(W.F64)
 
     # plain FP64 path: one instance at a time, one launch per step
@@ -170,8 +203,10 @@ def main():
     k_ms = float(np.mean(r32["kernel_ms"]))
     achieved = r32["flops_pass"] / (k_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
-                "kernel": "k_resident<5,float,double>", "kernel_ms": k_ms}
+                "frac": achieved / PEAK_VALU_TFLOPS, "traffic": measured_traffic(),
+                "traffic_unit": "HBM bytes per pass",
+                "kernel": "k_resident<5, D, P, float, double>: KdV (D 5) and mKdV (D 9, odd) launches of one pass",
+                "kernel_ms": k_ms, "flops_per_pass": r32["flops_pass"]}
     out = {
         "metric": "lattice-node updates/s, batched FP32 vs plain FP64 on 1 GPU; p50/p99 latency",
         "value": r32["nu_per_s"],
