@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=int, default=16)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy 1 GiB device to device first (reference kernel for HBM counters)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the planner's automatic settings instead of autotuning the batch first")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the FP32 batch (for profiler runs); prints a reduced line")
     args = ap.parse_args()
@@ -144,6 +146,7 @@ def main():
 
     def run(prec):
         insts, b = build_batch(prec)
+        tuning = None if args.no_autotune else b.autotune(LB_STEPS)
         nu_pass = sum(x.problem.n for x in insts) * LB_STEPS
         fpn = {}
         for x in insts:
@@ -163,7 +166,8 @@ def main():
         st = [b.read_phi(i)[1] for i in (0, args.count - 1)]
         b.close()
         return {"nu_pass": nu_pass, "flops_pass": flops_pass, "wall_s": wall, "kernel_ms": kern_ms,
-                "nu_per_s": nu_pass * args.steps / wall, "status_ok": all(s == lbm.OK for s in st)}
+                "nu_per_s": nu_pass * args.steps / wall, "status_ok": all(s == lbm.OK for s in st),
+                "tuning": tuning}
 
     r32 = run(W.F32_DEV)
     if args.batch_only:
@@ -226,9 +230,11 @@ def main():
                    "instances": args.count, "lattice_steps_per_step": LB_STEPS,
                    "node_updates_per_step": r32["nu_pass"]},
         "fp64_batched": {"value": r64["nu_per_s"], "ms_per_step": r64["wall_s"] / args.steps * 1e3,
-                         "kernel_ms": float(np.mean(r64["kernel_ms"]))},
+                         "kernel_ms": float(np.mean(r64["kernel_ms"])), "autotune": r64["tuning"]},
+        "autotune": r32["tuning"],
         "plain_fp64": {"value": plain, "sample_instances": int(len(sample)),
-                       "path": "one fused collide+stream launch per step, one instance at a time"},
+                       "path": "one fused collide+stream launch per step (64-step blocks replayed from a HIP graph), "
+                               "one instance at a time"},
         "speedup_vs_plain_fp64": r32["nu_per_s"] / plain,
         "status_ok": bool(r32["status_ok"] and r64["status_ok"]),
         "roofline": roofline,

@@ -193,6 +193,28 @@ lbm_status lbm_batch_set_tiling(lbm_batch b, int32_t steps_per_launch, int32_t w
    not depend on either value (bitwise).  INVALID_ARG outside those ranges. */
 lbm_status lbm_batch_set_resident(lbm_batch b, int32_t max_workgroups, int32_t chunks);
 
+/* Autotuner result: the planner settings it kept (as set by lbm_batch_set_path,
+   lbm_batch_set_tiling and lbm_batch_set_resident) and the measured rates. */
+typedef struct {
+  int32_t path;                        /* 0 automatic, 1 HBM streaming, 3 temporal blocking */
+  int32_t tile_steps;                  /* steps per tiled launch (0 = automatic) */
+  int32_t tile_wgs;                    /* tiled workgroups per CU (0 = automatic) */
+  int32_t res_chunks;                  /* resident step chunks (0 = automatic) */
+  int32_t candidates;                  /* configurations timed */
+  int32_t pad_;
+  double best_node_updates_per_s;      /* device rate of the kept settings */
+  double default_node_updates_per_s;   /* device rate of the automatic settings */
+} lbm_tuning;
+
+/* Times candidate planner settings -- the temporal-blocking tile (steps per
+   launch, workgroups per CU), the resident step chunking and, for at most 16
+   instances, HBM streaming instead of LDS residency -- on a copy of the batch
+   advanced probe_steps per candidate (best of two passes after a warm-up),
+   and applies the fastest to b (a candidate must beat the best so far by 3%).  The state of b is not changed.  Needs device
+   memory for a second copy of the batch (OUT_OF_MEMORY otherwise); synchronises
+   b's stream; UNSUPPORTED for the batch behind a server.  out may be NULL. */
+lbm_status lbm_batch_autotune(lbm_batch b, int64_t probe_steps, lbm_tuning* out);
+
 lbm_status lbm_batch_destroy(lbm_batch b);
 
 /* ---- serving: continuous batching of solve requests -------------------- */

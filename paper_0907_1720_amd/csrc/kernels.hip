@@ -438,6 +438,18 @@ hipError_t launch_stream_q(int code, const T* fin, T* fout, int n, int stride, c
 }
 
 template <int Q, typename T, typename A>
+const void* stream_fn(int code) {
+  switch (code) {
+#define LBM_CASE(DD, PP) \
+  case DD | (PP << 8):   \
+    return (const void*)k_stream<Q, DD, PP, T, A>;
+    LBM_VARIANT_CASES
+#undef LBM_CASE
+  }
+  return nullptr;
+}
+
+template <int Q, typename T, typename A>
 const void* resident_fn(int code) {
   switch (code) {
 #define LBM_CASE(DD, PP) \
@@ -481,6 +493,17 @@ hipError_t launch_stream(int q, int D, int prec, const void* fin, void* fout, in
                   : launch_stream_q<7, float, double>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
   return q == 5 ? launch_stream_q<5, float, float>(D, (const float*)fin, (float*)fout, n, stride, cf, s)
                 : launch_stream_q<7, float, float>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
+}
+
+const void* stream_kernel(int q, int code, int prec) {
+  if (q == 5) {
+    if (prec == 0) return stream_fn<5, double, double>(code);
+    if (prec == 1) return stream_fn<5, float, double>(code);
+    return stream_fn<5, float, float>(code);
+  }
+  if (prec == 0) return stream_fn<7, double, double>(code);
+  if (prec == 1) return stream_fn<7, float, double>(code);
+  return stream_fn<7, float, float>(code);
 }
 
 hipError_t launch_resident(int q, int prec, int code, const DevJob* jobs, const DevJobInst* jinst, int njobs,

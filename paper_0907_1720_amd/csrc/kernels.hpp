@@ -49,6 +49,10 @@ hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n
 // `code` = variant_code(D, parity) of the relaxation polynomial
 hipError_t launch_stream(int q, int code, int prec, const void* fin, void* fout, int n, int stride,
                          const DevCoef* cf, hipStream_t s);
+// the fused collide+stream kernel of variant `code` (arguments: const T* fin,
+// T* fout, int n, int stride, const DevCoef* cf; 256 threads per block), for
+// graph nodes; nullptr for an unknown variant
+const void* stream_kernel(int q, int code, int prec);
 // persistent launch over `njobs` jobs (bin-packed instances of one variant
 // `code`), each split into `nchunks` step chunks; done[0..njobs) starts at 0
 hipError_t launch_resident(int q, int prec, int code, const DevJob* jobs, const DevJobInst* jinst, int njobs,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -45,6 +46,26 @@ struct HostInst {
   int cur = 0;      // which of the two state buffers is current
   int64_t steps_done = 0;
 };
+
+// A block of kStepBlock fused collide+stream launches of one instance as a
+// HIP graph (the streaming path is launch bound for small grids): replayed
+// whole, it advances the instance kStepBlock steps and, kStepBlock being even,
+// leaves its state in the buffer it started from.
+constexpr int kStepBlock = 64;
+struct StepGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* fin = nullptr;    // what the graph was built for
+  const void* fout = nullptr;
+  const void* cf = nullptr;
+  int n = 0, stride = 0, code = -1, q = 0, prec = -1;
+};
+
+void release_graph(StepGraph* g) {
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  *g = StepGraph{};
+}
 
 struct DeviceLimits {
   int cus = 0;
@@ -110,6 +131,7 @@ struct lbm_batch_s {
   hipEvent_t join[kAuxStreams] = {};
   float last_ms = 0.0f;
   std::vector<DevCoef> hcoef;
+  std::vector<StepGraph> step_graphs;   // per instance and current-buffer parity
 };
 
 struct lbm_problem_s {
@@ -184,6 +206,7 @@ void destroy_batch(lbm_batch_s* b) {
   if (b->items_host) hipHostFree(b->items_host);
   hipFree(b->jobs);
   hipFree(b->done);
+  for (StepGraph& g : b->step_graphs) release_graph(&g);
   if (b->jobs_host) hipHostFree(b->jobs_host);
   for (int k = 0; k < 2; ++k)
     if (b->items_done[k]) hipEventDestroy(b->items_done[k]);
@@ -383,6 +406,66 @@ lbm_status load_phi_one(lbm_batch_s* b, int i, const double* phi, int on_device)
 
 bool fits_resident(const lbm_batch_s* b, const HostInst& h) {
   return (size_t)h.q * h.n * elem_size(h) + resident_static_lds(h.q, h.prec, h.D) <= b->lim.lds_max;
+}
+
+// The step-block graph of instance i for its current buffer, built on first use
+// and rebuilt when the instance's buffers, coefficients or shape changed.
+lbm_status step_graph(lbm_batch_s* b, int i, StepGraph** out) {
+  const HostInst& h = b->inst[i];
+  if (b->step_graphs.size() < 2 * b->inst.size()) b->step_graphs.resize(2 * b->inst.size());
+  StepGraph* g = &b->step_graphs[2 * i + h.cur];
+  const void* fin = state_cur(b, h);
+  const void* fout = state_other(b, h);
+  const void* cf = b->coefs + i;
+  if (g->exec && g->fin == fin && g->fout == fout && g->cf == cf && g->n == h.n && g->stride == h.stride &&
+      g->code == h.D && g->q == h.q && g->prec == h.prec) {
+    *out = g;
+    return LBM_OK;
+  }
+  if (g->exec) LBM_HIP(hipStreamSynchronize(b->stream));   // a replay of the stale graph may be in flight
+  release_graph(g);
+  const void* fn = stream_kernel(h.q, h.D, h.prec);
+  if (!fn) return LBM_ERR_UNSUPPORTED;
+  struct Args { const void* in; void* out; int n; int stride; const void* cf; };
+  std::vector<Args> args(kStepBlock);
+  std::vector<void*> ptrs(5 * kStepBlock);
+  LBM_HIP(hipGraphCreate(&g->graph, 0));
+  hipGraphNode_t prev = nullptr;
+  for (int k = 0; k < kStepBlock; ++k) {
+    Args& a = args[k];
+    a.in = (k & 1) ? fout : fin;
+    a.out = const_cast<void*>((k & 1) ? fin : fout);
+    a.n = h.n;
+    a.stride = h.stride;
+    a.cf = cf;
+    void** p = &ptrs[5 * k];
+    p[0] = &a.in;
+    p[1] = &a.out;
+    p[2] = &a.n;
+    p[3] = &a.stride;
+    p[4] = &a.cf;
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(fn);
+    kp.gridDim = dim3((h.n + 255) / 256);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = p;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    LBM_HIP(hipGraphAddKernelNode(&node, g->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+    prev = node;
+  }
+  LBM_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  g->fin = fin;
+  g->fout = fout;
+  g->cf = cf;
+  g->n = h.n;
+  g->stride = h.stride;
+  g->code = h.D;
+  g->q = h.q;
+  g->prec = h.prec;
+  *out = g;
+  return LBM_OK;
 }
 
 constexpr int64_t kMaxStepsPerLaunch = int64_t(1) << 30;
@@ -681,12 +764,20 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     }
   }
   LBM_HIP(hipEventRecord(b->items_done[k], b->stream));
-  // streaming instances: one fused collide+stream launch per step
+  // streaming instances: one fused collide+stream launch per step, whole
+  // blocks of kStepBlock steps replayed from a graph
   for (int i : str) {
     HostInst& h = b->inst[i];
     lbm_status s = ensure_second_buffer(b, h.f32);
     if (s != LBM_OK) return s;
-    for (int64_t t = 0; t < steps[i]; ++t) {
+    int64_t t = 0;
+    if (steps[i] >= 2 * kStepBlock) {
+      StepGraph* g = nullptr;
+      s = step_graph(b, i, &g);
+      if (s != LBM_OK) return s;
+      for (; t + kStepBlock <= steps[i]; t += kStepBlock) LBM_HIP(hipGraphLaunch(g->exec, b->stream));
+    }
+    for (; t < steps[i]; ++t) {
       LBM_HIP(launch_stream(h.q, h.D, h.prec, state_cur(b, h), state_other(b, h), h.n, h.stride, b->coefs + i,
                             b->stream));
       h.cur = 1 - h.cur;
@@ -738,6 +829,146 @@ lbm_status read_phi(lbm_batch_s* b, int i, double* out, int on_device, lbm_statu
   lbm_status s = (flags[0] || flags[1]) ? LBM_ERR_NONFINITE : LBM_OK;
   if (inst_status) *inst_status = s;
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning: time candidate planner settings on a copy of the batch (same
+// descriptors, coefficients and state) and keep the fastest.  The planner's
+// choices it covers: the tile shape and steps per launch of the temporal-
+// blocking path (instances that do not fit one workgroup's LDS), the step
+// chunking of the resident path, and -- for small batches -- the LDS-resident
+// vs HBM-streaming choice itself.
+// ---------------------------------------------------------------------------
+struct Knobs {
+  int path, tile_steps, tile_wgs, res_grid, res_chunks;
+};
+constexpr double kTuneMargin = 0.97;
+
+Knobs knobs_of(const lbm_batch_s* b) { return Knobs{b->path, b->tile_steps, b->tile_wgs, b->res_grid, b->res_chunks}; }
+
+void set_knobs(lbm_batch_s* b, const Knobs& k) {
+  b->path = k.path;
+  b->tile_steps = k.tile_steps;
+  b->tile_wgs = k.tile_wgs;
+  b->res_grid = k.res_grid;
+  b->res_chunks = k.res_chunks;
+}
+
+lbm_status clone_for_tuning(lbm_batch_s* b, lbm_batch_s** out) {
+  const int count = (int)b->inst.size();
+  std::vector<lbm_desc> d(count);
+  for (int i = 0; i < count; ++i) d[i] = b->inst[i].desc;
+  lbm_batch_s* c = nullptr;
+  lbm_status s = create_batch(d.data(), count, b->stream, nullptr, 0, &c);
+  if (s != LBM_OK) return s;
+  // same descriptors in the same order: same layout; copy coefficients and state
+  for (int i = 0; i < count && s == LBM_OK; ++i) {
+    c->inst[i].mdl = b->inst[i].mdl;
+    c->inst[i].cur = b->inst[i].cur;
+    c->hcoef[i] = b->hcoef[i];
+  }
+  auto copy = [&](void* dst, const void* src, size_t bytes) -> lbm_status {
+    if (!bytes) return LBM_OK;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, b->stream) == hipSuccess ? LBM_OK
+                                                                                           : LBM_ERR_DEVICE;
+  };
+  if (s == LBM_OK) s = copy(c->coefs, b->coefs, sizeof(DevCoef) * count);
+  for (int k = 0; k < 2 && s == LBM_OK; ++k) {
+    if (b->f64[k]) {
+      if (k == 1) s = ensure_second_buffer(c, false);
+      if (s == LBM_OK) s = copy(c->f64[k], b->f64[k], sizeof(double) * b->n64);
+    }
+    if (b->f32[k] && s == LBM_OK) {
+      if (k == 1) s = ensure_second_buffer(c, true);
+      if (s == LBM_OK) s = copy(c->f32[k], b->f32[k], sizeof(float) * b->n32);
+    }
+  }
+  if (s == LBM_OK && hipStreamSynchronize(b->stream) != hipSuccess) s = LBM_ERR_DEVICE;
+  if (s != LBM_OK) {
+    destroy_batch(c);
+    return s;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+// device time (ms) of one pass of `probe` steps with knobs k: best of two after a warm-up pass
+lbm_status time_knobs(lbm_batch_s* c, const Knobs& k, int64_t probe, double* ms) {
+  set_knobs(c, k);
+  std::vector<int64_t> st(c->inst.size(), probe);
+  double best = 1e300;
+  for (int r = 0; r < 3; ++r) {
+    lbm_status s = advance(c, st.data());
+    if (s != LBM_OK) return s;
+    LBM_HIP(hipEventSynchronize(c->ev1));
+    float t = 0.0f;
+    LBM_HIP(hipEventElapsedTime(&t, c->ev0, c->ev1));
+    if (r > 0) best = std::min(best, (double)t);
+  }
+  *ms = best;
+  return LBM_OK;
+}
+
+lbm_status autotune(lbm_batch_s* b, int64_t probe, lbm_tuning* out) {
+  const int count = (int)b->inst.size();
+  bool any_fit = false, any_big = false;
+  double nodes = 0.0;
+  int64_t minn = INT64_MAX;
+  for (const HostInst& h : b->inst) {
+    const bool f = fits_resident(b, h);
+    any_fit |= f;
+    any_big |= !f;
+    nodes += h.n;
+    minn = std::min<int64_t>(minn, h.n);
+  }
+  lbm_batch_s* c = nullptr;
+  lbm_status s = clone_for_tuning(b, &c);
+  if (s != LBM_OK) return s;
+  int tried = 0;
+  Knobs best{0, 0, 0, 0, 0};
+  double best_ms = 0.0, default_ms = 0.0;
+  s = time_knobs(c, best, probe, &default_ms);
+  best_ms = default_ms;
+  ++tried;
+  auto consider = [&](const Knobs& k) {
+    if (s != LBM_OK) return;
+    double ms = 0.0;
+    s = time_knobs(c, k, probe, &ms);
+    ++tried;
+    if (s == LBM_OK && ms < kTuneMargin * best_ms) {   // clear wins only, not timing noise
+      best_ms = ms;
+      best = k;
+    }
+  };
+  // 1. temporal blocking: steps per launch x workgroups per CU
+  if (any_big || minn >= 1024) {
+    static const int kTiles[][2] = {{8, 2}, {16, 2}, {32, 2}, {64, 2}, {16, 1}, {32, 1}, {64, 1}};
+    const int path = any_big ? best.path : 3;   // instances that fit: try them tiled as well
+    for (const auto& t : kTiles) consider(Knobs{path, t[0], t[1], 0, 0});
+    if (!any_big) consider(Knobs{3, 0, 0, 0, 0});
+  }
+  // 2. resident step chunks
+  if (any_fit && best.path != 3) {
+    static const int kChunks[] = {1, 4, 8, 16, 32};
+    const Knobs base = best;
+    for (int ch : kChunks) consider(Knobs{base.path, base.tile_steps, base.tile_wgs, 0, ch});
+  }
+  // 3. HBM streaming, one launch per step: only for a few instances
+  if (count <= 16 && nodes * (double)probe <= 2.5e8) consider(Knobs{1, 0, 0, 0, 0});
+  destroy_batch(c);
+  if (s != LBM_OK) return s;
+  set_knobs(b, best);
+  if (out) {
+    out->path = best.path;
+    out->tile_steps = best.tile_steps;
+    out->tile_wgs = best.tile_wgs;
+    out->res_chunks = best.res_chunks;
+    out->candidates = tried;
+    out->pad_ = 0;
+    out->best_node_updates_per_s = nodes * (double)probe / (best_ms * 1e-3);
+    out->default_node_updates_per_s = nodes * (double)probe / (default_ms * 1e-3);
+  }
+  return LBM_OK;
 }
 
 }  // namespace
@@ -972,6 +1203,12 @@ lbm_status lbm_batch_set_tiling(lbm_batch b, int32_t steps_per_launch, int32_t w
   b->tile_steps = steps_per_launch;
   b->tile_wgs = wgs_per_cu;
   return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch b, int64_t probe_steps, lbm_tuning* out) {
+  if (!b || probe_steps < 1 || probe_steps > kMaxStepsPerLaunch) return LBM_ERR_INVALID_ARG;
+  if (b->arena[0]) return LBM_ERR_UNSUPPORTED;   // server-owned batches re-plan every block
+  return autotune(b, probe_steps, out);
 }
 
 lbm_status lbm_batch_set_resident(lbm_batch b, int32_t max_workgroups, int32_t chunks) {

@@ -40,6 +40,19 @@ class LbmDesc(ctypes.Structure):
     ]
 
 
+class LbmTuning(ctypes.Structure):
+    _fields_ = [
+        ("path", ctypes.c_int32),
+        ("tile_steps", ctypes.c_int32),
+        ("tile_wgs", ctypes.c_int32),
+        ("res_chunks", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("best_node_updates_per_s", ctypes.c_double),
+        ("default_node_updates_per_s", ctypes.c_double),
+    ]
+
+
 class LBMError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -88,6 +101,7 @@ def library() -> ctypes.CDLL:
         "lbm_batch_set_path": (I32, [P, I32]),
         "lbm_batch_set_tiling": (I32, [P, I32, I32]),
         "lbm_batch_set_resident": (I32, [P, I32, I32]),
+        "lbm_batch_autotune": (I32, [P, I64, P]),
         "lbm_batch_destroy": (I32, [P]),
         "lbm_server_create": (I32, [P, SZ, I32, I64, I32, P]),
         "lbm_server_submit": (I32, [P, DP, P, I64, P]),
@@ -299,6 +313,18 @@ class Batch:
     def set_resident(self, max_workgroups: int = 0, chunks: int = 0):
         _check(library().lbm_batch_set_resident(self._h, int(max_workgroups), int(chunks)),
                "lbm_batch_set_resident")
+
+    def autotune(self, probe_steps: int) -> dict:
+        """Times planner settings on a copy of the batch and keeps the fastest."""
+        t = LbmTuning()
+        _check(library().lbm_batch_autotune(self._h, int(probe_steps), ctypes.byref(t)), "lbm_batch_autotune")
+        return {k: getattr(t, k) for k, _ in LbmTuning._fields_ if k != "pad_"}
+
+    def apply_tuning(self, t: dict):
+        """Sets the planner settings of an earlier autotune result."""
+        self.set_path(t["path"])
+        self.set_tiling(t["tile_steps"], t["tile_wgs"])
+        self.set_resident(0, t["res_chunks"])
 
     def last_advance_ms(self) -> float:
         ms = ctypes.c_float()

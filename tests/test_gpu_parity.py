@@ -246,6 +246,60 @@ def test_resident_step_chunks_bitwise(prec):
             assert np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("prec", [W.F64, W.F32_DEV])
+def test_streaming_step_graphs_match_resident(prec):
+    """The streaming path replays 64-step blocks from a HIP graph (and runs the
+    remainder eagerly).  Several calls of mixed length, with reads (host
+    synchronisation) between them, must equal the resident path after every
+    call, bitwise."""
+    insts = _config2(prec, 3)
+    bs = []
+    for path in (lbm.PATH_STREAM, lbm.PATH_RESIDENT):
+        b = lbm.Batch([i.problem for i in insts])
+        b.set_path(path)
+        b.load_phi([i.phi0 for i in insts])
+        bs.append(b)
+    for steps in (200, 333, 128, 64, 129, 0, 256):
+        say("case step graphs", prec, steps)
+        for b in bs:
+            b.advance(steps)
+        for k in range(len(insts)):
+            a, sa = bs[0].read_phi(k)
+            c, sc = bs[1].read_phi(k)
+            assert sa == lbm.OK and sc == lbm.OK
+            assert np.array_equal(a, c), (steps, k)
+    for b in bs:
+        b.close()
+
+
+def test_autotune_leaves_state_and_results_unchanged():
+    """The tuner times candidates on a copy: the batch's state is untouched,
+    and the settings it keeps give the same results as the automatic ones."""
+    insts = _config2(W.F32_DEV, 6) + [W.config4_instance(i, prec=W.F32_DEV) for i in (1, 3)]
+    probs = [i.problem for i in insts]
+    tuned = lbm.Batch(probs)
+    plain = lbm.Batch(probs)
+    for b in (tuned, plain):
+        b.load_phi([i.phi0 for i in insts])
+        b.advance(17)
+    before = [tuned.read_phi(k)[0] for k in range(len(insts))]
+    t = tuned.autotune(64)
+    say("  tuning", t)
+    assert t["candidates"] >= 2
+    assert t["best_node_updates_per_s"] >= t["default_node_updates_per_s"] > 0
+    for k in range(len(insts)):
+        assert np.array_equal(tuned.read_phi(k)[0], before[k])
+    for b in (tuned, plain):
+        b.advance(301)
+    for k in range(len(insts)):
+        a, sa = tuned.read_phi(k)
+        c, sc = plain.read_phi(k)
+        assert sa == lbm.OK and sc == lbm.OK
+        assert np.array_equal(a, c), k
+    tuned.close()
+    plain.close()
+
+
 def test_resident_parameters_validated():
     insts = _config2(W.F64, 2)
     b = lbm.Batch([i.problem for i in insts])
