@@ -49,7 +49,13 @@ typedef enum {
   LBM_ERR_BUSY = 7           /* serving: request not admitted yet / not finished */
 } lbm_status;
 
-typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_DIRICHLET_EQ = 1 } lbm_bc;
+/* Boundaries.  Periodic: x_i = x0 + i dx, i = 0..n-1, node n-1 neighbours node 0.
+   The bounded kinds (the exact-solution boundaries of Sec. IV) take a grid that
+   includes both end points and reset the outer layers after every step from
+   values the caller supplies (lbm_advance_bounded): DIRICHLET_EQ sets
+   f = f_eq(phi*) there, DIRICHLET_NEE sets f = f_eq(phi*) + (f - f_eq(phi)) of
+   the first interior node (non-equilibrium extrapolation). */
+typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_DIRICHLET_EQ = 1, LBM_BC_DIRICHLET_NEE = 2 } lbm_bc;
 /* LBM_F64: FP64 state and arithmetic.  LBM_F32_DEV: the state is stored in
    FP32 as the deviation g = f - f_rest from the equilibrium of a rest state
    phi_rest (the mean of phi0, conserved on a periodic grid); the zeroth
@@ -75,7 +81,7 @@ typedef struct {
   double pi_coef[7][5];
   int64_t n;             /* nodes on the periodic grid, n >= q */
   double dx, dt, tau;    /* lattice speed c = dx/dt (Sec. II.A); tau > 1/2 */
-  int32_t bc;            /* lbm_bc; only LBM_BC_PERIODIC is implemented */
+  int32_t bc;            /* lbm_bc */
   int32_t prec;          /* lbm_precision */
 } lbm_desc;
 
@@ -125,8 +131,20 @@ lbm_status lbm_create(const lbm_desc* d, void* stream, void* dev_buf, size_t buf
    doubles on the host (phi_on_device = 0) or the device (1). */
 lbm_status lbm_load_phi(lbm_problem h, const double* phi, int phi_on_device);
 
-/* Advance `steps` time steps (asynchronous on the problem's stream). */
+/* Advance `steps` time steps (asynchronous on the problem's stream).
+   INVALID_ARG for a bounded problem (those advance with lbm_advance_bounded). */
 lbm_status lbm_advance(lbm_problem h, int64_t steps);
+
+/* Bounded problems (bc = LBM_BC_DIRICHLET_EQ or _NEE; Sec. IV): advance `steps`
+   steps; after step s (s = 1..steps) the `layers` outer nodes at each end are
+   reset from the exact solution phib[(s-1) * 2 layers + k]: k < layers holds
+   nodes 0..layers-1, k >= layers nodes n-layers..n-1, at time s dt after the
+   steps already taken.  phib is a host array of steps * 2 * layers doubles,
+   copied before the call returns.  layers = 0 means q/2; layers must lie in
+   [q/2, 32] and n >= 2 layers + 2.  Each step is one fused collide+stream
+   launch through HBM plus one boundary launch.  INVALID_ARG for a periodic
+   problem or bad sizes. */
+lbm_status lbm_advance_bounded(lbm_problem h, int64_t steps, const double* phib, int32_t layers);
 
 /* phi = sum_j f_j (zeroth moment, FP64) into n doubles on the host or device.
    Synchronises; returns LBM_ERR_NONFINITE (after writing) if any value is NaN/Inf. */

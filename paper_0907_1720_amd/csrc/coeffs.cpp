@@ -166,7 +166,8 @@ lbm_status build_model(const lbm_desc& d, Model* out) {
   if (d.scheme < 0 || d.scheme > 2 || (d.am != LBM_AM_CORRECTED && d.am != LBM_AM_PAPER))
     return LBM_ERR_INVALID_ARG;
   if (d.prec != LBM_F64 && d.prec != LBM_F32_DEV && d.prec != LBM_F32_DEV_ARITH32) return LBM_ERR_INVALID_ARG;
-  if (d.bc != LBM_BC_PERIODIC) return d.bc == LBM_BC_DIRICHLET_EQ ? LBM_ERR_UNSUPPORTED : LBM_ERR_INVALID_ARG;
+  if (d.bc != LBM_BC_PERIODIC && d.bc != LBM_BC_DIRICHLET_EQ && d.bc != LBM_BC_DIRICHLET_NEE)
+    return LBM_ERR_INVALID_ARG;
   for (int k = 1; k <= 6; ++k) {
     if (d.pi_deg[k] < -1 || d.pi_deg[k] > 4) return LBM_ERR_INVALID_ARG;
     for (int p = 0; p <= d.pi_deg[k]; ++p)

@@ -2,6 +2,7 @@
 // Guo (Sec. II.A eq. LBE with the equilibria of Sec. III) and its read-outs.
 //
 //  k_init      f := f_eq(phi)                        (initial distribution)
+//  k_bound     exact-solution boundary layers of a bounded domain
 //  k_stream    one fused collide+stream step, state in HBM, SoA rows,
 //              coalesced loads, shifted stores with periodic wrap
 //  k_resident  persistent work-queue kernel over jobs (instances bin-packed
@@ -27,6 +28,42 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi, T*
   const double p = phi[x] - cf->phi_rest;   // phi_rest = 0 for FP64 storage
 #pragma unroll
   for (int j = 0; j < Q; ++j) f[(int64_t)j * stride + x] = (T)poly_eval<D, 0, double>(cf->init[j], p);
+}
+
+// ---------------------------------------------------------------------------
+// Bounded domains (exact-solution boundaries of Sec. IV): after a step the
+// `layers` outer nodes at each end are reset from the exact solution phi* at
+// the new time -- kind 1: f = f_eq(phi*); kind 2 (non-equilibrium
+// extrapolation): f = f_eq(phi*) + (f - f_eq(phi)) taken at the first interior
+// node.  One thread per boundary node; phib = {left layers, right layers}.
+// The stored value is the one k_init stores: f (FP64) or f - f_rest (FP32).
+// ---------------------------------------------------------------------------
+template <int Q, int D, typename T>
+__global__ __launch_bounds__(64) void k_bound(T* __restrict__ f, int n, int stride, int layers, int kind,
+                                              const double* __restrict__ phib, const DevCoef* __restrict__ cf) {
+  const int t = threadIdx.x;
+  if (t >= 2 * layers) return;
+  const bool left = t < layers;
+  const int x = left ? t : n - 2 * layers + t;
+  const int inner = left ? layers : n - 1 - layers;
+  double neq[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) neq[j] = 0.0;
+  if (kind == 2) {
+    double g[Q];
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      g[j] = (double)f[(int64_t)j * stride + inner];
+      s += g[j];
+    }
+    // s = phi - phi_rest (phi itself for FP64 storage)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) neq[j] = g[j] - poly_eval<D, 0, double>(cf->init[j], s);
+  }
+  const double p = phib[t] - cf->phi_rest;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) f[(int64_t)j * stride + x] = (T)(poly_eval<D, 0, double>(cf->init[j], p) + neq[j]);
 }
 
 // ---------------------------------------------------------------------------
@@ -480,6 +517,32 @@ hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n
                   : launch_init_q<7, double>(D, phi, (double*)f, n, stride, cf, s);
   return q == 5 ? launch_init_q<5, float>(D, phi, (float*)f, n, stride, cf, s)
                 : launch_init_q<7, float>(D, phi, (float*)f, n, stride, cf, s);
+}
+
+namespace {
+template <int Q, typename T>
+hipError_t launch_bound_q(int D, T* f, int n, int stride, int layers, int kind, const double* phib,
+                          const DevCoef* cf, hipStream_t s) {
+  switch (D) {
+#define LBM_CASE(DD) \
+  case DD:           \
+    k_bound<Q, DD, T><<<1, 64, 0, s>>>(f, n, stride, layers, kind, phib, cf); \
+    return hipGetLastError();
+    LBM_INIT_CASES
+#undef LBM_CASE
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_bound(int q, int D, int prec, void* f, int n, int stride, int layers, int kind,
+                        const double* phib, const DevCoef* cf, hipStream_t s) {
+  if (layers < 1 || 2 * layers > 64) return hipErrorInvalidValue;
+  if (prec == 0)
+    return q == 5 ? launch_bound_q<5, double>(D, (double*)f, n, stride, layers, kind, phib, cf, s)
+                  : launch_bound_q<7, double>(D, (double*)f, n, stride, layers, kind, phib, cf, s);
+  return q == 5 ? launch_bound_q<5, float>(D, (float*)f, n, stride, layers, kind, phib, cf, s)
+                : launch_bound_q<7, float>(D, (float*)f, n, stride, layers, kind, phib, cf, s);
 }
 
 hipError_t launch_stream(int q, int D, int prec, const void* fin, void* fout, int n, int stride,

@@ -46,6 +46,10 @@ inline int variant_code(int D, int parity) { return D | (parity << 8); }
 // relaxation; 2 = FP32 deviation storage, FP32 relaxation.
 hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n, int stride,
                        const DevCoef* cf, hipStream_t s);
+// bounded domains: reset `layers` (1..32) nodes at each end from phib[0 .. 2 layers)
+// (kind 1 equilibrium, 2 non-equilibrium extrapolation); D = init degree
+hipError_t launch_bound(int q, int D, int prec, void* f, int n, int stride, int layers, int kind,
+                        const double* phib, const DevCoef* cf, hipStream_t s);
 // `code` = variant_code(D, parity) of the relaxation polynomial
 hipError_t launch_stream(int q, int code, int prec, const void* fin, void* fout, int n, int stride,
                          const DevCoef* cf, hipStream_t s);

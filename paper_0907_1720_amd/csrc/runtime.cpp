@@ -132,6 +132,8 @@ struct lbm_batch_s {
   float last_ms = 0.0f;
   std::vector<DevCoef> hcoef;
   std::vector<StepGraph> step_graphs;   // per instance and current-buffer parity
+  double* bound = nullptr;              // boundary values of bounded problems (device)
+  size_t bound_cap = 0;                 // doubles
 };
 
 struct lbm_problem_s {
@@ -207,6 +209,7 @@ void destroy_batch(lbm_batch_s* b) {
   hipFree(b->jobs);
   hipFree(b->done);
   for (StepGraph& g : b->step_graphs) release_graph(&g);
+  hipFree(b->bound);
   if (b->jobs_host) hipHostFree(b->jobs_host);
   for (int k = 0; k < 2; ++k)
     if (b->items_done[k]) hipEventDestroy(b->items_done[k]);
@@ -483,6 +486,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   for (int i = 0; i < count; ++i) {
     if (steps[i] == 0) continue;
     const HostInst& h = b->inst[i];
+    if (h.desc.bc != LBM_BC_PERIODIC) return LBM_ERR_INVALID_ARG;   // bounded: lbm_advance_bounded
     const bool fits = fits_resident(b, h);
     if (b->path == 2 && !fits) return LBM_ERR_UNSUPPORTED;
     if (b->path == 1)
@@ -1064,6 +1068,43 @@ lbm_status lbm_advance(lbm_problem h, int64_t steps) {
   return advance(h->b, &steps);
 }
 
+lbm_status lbm_advance_bounded(lbm_problem h, int64_t steps, const double* phib, int32_t layers) {
+  if (!h || steps < 0 || (steps > 0 && !phib)) return LBM_ERR_INVALID_ARG;
+  lbm_batch_s* b = h->b;
+  HostInst& in = b->inst[0];
+  if (in.desc.bc != LBM_BC_DIRICHLET_EQ && in.desc.bc != LBM_BC_DIRICHLET_NEE) return LBM_ERR_INVALID_ARG;
+  const int H = in.q / 2;
+  if (layers == 0) layers = H;
+  if (layers < H || layers > 32 || in.n < 2 * layers + 2) return LBM_ERR_INVALID_ARG;
+  if (steps == 0) return LBM_OK;
+  lbm_status s = ensure_second_buffer(b, in.f32);
+  if (s != LBM_OK) return s;
+  const size_t need = (size_t)steps * 2 * layers;
+  if (need > b->bound_cap) {
+    LBM_HIP(hipStreamSynchronize(b->stream));   // earlier boundary launches may still read the old buffer
+    hipFree(b->bound);
+    b->bound = nullptr;
+    b->bound_cap = 0;
+    if (hipMalloc(&b->bound, sizeof(double) * need) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+    b->bound_cap = need;
+  }
+  // a synchronous copy: the previous call's launches have read the buffer by the time it lands
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  LBM_HIP(hipMemcpy(b->bound, phib, sizeof(double) * need, hipMemcpyHostToDevice));
+  const int kind = in.desc.bc == LBM_BC_DIRICHLET_EQ ? 1 : 2;
+  LBM_HIP(hipEventRecord(b->ev0, b->stream));
+  for (int64_t t = 0; t < steps; ++t) {
+    LBM_HIP(launch_stream(in.q, in.D, in.prec, state_cur(b, in), state_other(b, in), in.n, in.stride, b->coefs,
+                          b->stream));
+    in.cur = 1 - in.cur;
+    LBM_HIP(launch_bound(in.q, in.Dinit, in.prec, state_cur(b, in), in.n, in.stride, layers, kind,
+                         b->bound + (size_t)t * 2 * layers, b->coefs, b->stream));
+  }
+  LBM_HIP(hipEventRecord(b->ev1, b->stream));
+  in.steps_done += steps;
+  return LBM_OK;
+}
+
 lbm_status lbm_read_phi(lbm_problem h, double* out, int out_on_device) {
   if (!h || !out) return LBM_ERR_INVALID_ARG;
   return read_phi(h->b, 0, out, out_on_device, nullptr);
@@ -1373,6 +1414,7 @@ lbm_status lbm_server_submit(lbm_server sv, const lbm_desc* d, const double* phi
   lbm_status s = build_model(*d, &m);
   if (s != LBM_OK) return s;
   if (d->n > sv->max_n) return LBM_ERR_INVALID_ARG;
+  if (d->bc != LBM_BC_PERIODIC) return LBM_ERR_UNSUPPORTED;   // requests carry no boundary data
   if (state_bytes_of(*d) > sv->arena.size) return LBM_ERR_OUT_OF_MEMORY;
   for (int64_t i = 0; i < d->n; ++i)
     if (!std::isfinite(phi0[i])) return LBM_ERR_INVALID_ARG;

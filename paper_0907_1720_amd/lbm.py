@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblbmhpde.so")
 
 OK, INVALID_ARG, UNSUPPORTED, SINGULAR_TAU, OUT_OF_MEMORY, DEVICE, NONFINITE, BUSY = range(8)
 PATH_AUTO, PATH_STREAM, PATH_RESIDENT, PATH_TILED = 0, 1, 2, 3
+BC_PERIODIC, BC_DIRICHLET_EQ, BC_DIRICHLET_NEE = 0, 1, 2
 
 
 class LbmDesc(ctypes.Structure):
@@ -84,6 +85,7 @@ def library() -> ctypes.CDLL:
         "lbm_create": (I32, [DP, P, P, SZ, P]),
         "lbm_load_phi": (I32, [P, P, I32]),
         "lbm_advance": (I32, [P, I64]),
+        "lbm_advance_bounded": (I32, [P, I64, P, I32]),
         "lbm_read_phi": (I32, [P, P, I32]),
         "lbm_sum_phi": (I32, [P, P]),
         "lbm_state_bytes": (I32, [P, P]),
@@ -149,7 +151,7 @@ def make_desc(p: Problem) -> LbmDesc:
                 d.pi_coef[k][i] = float(c)
     d.n = int(p.n)
     d.dx, d.dt, d.tau = float(p.dx), float(p.dt), float(p.tau)
-    d.bc = 0
+    d.bc = int(getattr(p, "bc", 0))
     d.prec = int(p.prec)
     return d
 
@@ -218,6 +220,18 @@ class Solver:
 
     def advance(self, steps: int):
         _check(library().lbm_advance(self._h, int(steps)), "lbm_advance")
+
+    def advance_bounded(self, phib, layers: int = 0):
+        """Bounded problem: len(phib) steps; phib[s] = exact phi at the outer
+        `layers` nodes of each end (left then right) after step s + 1."""
+        a = np.ascontiguousarray(phib, dtype=np.float64)
+        steps = a.shape[0] if a.ndim == 2 else 0
+        if a.ndim != 2 or (steps and a.shape[1] % 2):
+            raise ValueError("phib must be (steps, 2 * layers)")
+        lay = a.shape[1] // 2 if steps else int(layers)
+        if layers and steps and lay != layers:
+            raise ValueError("phib width is not 2 * layers")
+        _check(library().lbm_advance_bounded(self._h, steps, a.ctypes.data, lay), "lbm_advance_bounded")
 
     def read_phi(self, out=None, allow_nonfinite: bool = False) -> np.ndarray:
         if out is not None and hasattr(out, "data_ptr"):

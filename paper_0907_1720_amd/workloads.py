@@ -47,6 +47,7 @@ class Problem:
     prec: int = F64
     x0: float = 0.0                     # x_i = x0 + i*dx
     name: str = ""
+    bc: int = 0                         # 0 periodic; 1 / 2 bounded: equilibrium / NEE layers
 
     def order(self) -> int:
         if self.m:

@@ -97,9 +97,10 @@ def test_validation_rejects_bad_descriptors():
     d = lbm.make_desc(good)
     d.pi_deg[1] = 5
     assert lib.lbm_validate(ctypes.byref(d)) == lbm.INVALID_ARG
-    d = lbm.make_desc(good)
-    d.bc = 1
-    assert lib.lbm_validate(ctypes.byref(d)) == lbm.UNSUPPORTED
+    for bc, want in ((1, lbm.OK), (2, lbm.OK), (3, lbm.INVALID_ARG), (-1, lbm.INVALID_ARG)):
+        d = lbm.make_desc(good)
+        d.bc = bc
+        assert lib.lbm_validate(ctypes.byref(d)) == want, bc
     d = lbm.make_desc(good)
     d.prec = 7
     assert lib.lbm_validate(ctypes.byref(d)) == lbm.INVALID_ARG
