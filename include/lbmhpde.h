@@ -162,12 +162,17 @@ lbm_status lbm_load_f(lbm_problem h, const void* host_buf, size_t bytes);
    workgroup's LDS, else temporal blocking), 1 = HBM streaming (one fused
    collide+stream launch per step), 2 = on-chip resident (all steps of a call
    in one launch; UNSUPPORTED if the state does not fit), 3 = temporal blocking
-   (tiles of the grid with halos advance several steps per launch in LDS). */
+   (tiles of the grid with halos advance several steps per launch in LDS),
+   4 = slabs (the grid split over workgroups that are resident together for
+   all steps of the call and exchange halos every few steps; the automatic
+   choice for grids larger than one workgroup's LDS, with temporal blocking
+   as the fallback when the slabs do not fit one launch). */
 lbm_status lbm_set_path(lbm_problem h, int32_t path);
 
-/* Temporal blocking parameters: steps per launch (0 = automatic, <= 4096) and
-   the number of workgroups per CU the 160 KiB LDS is split for (0 = automatic,
-   <= 8), which sets the tile width. */
+/* Temporal blocking and slab parameters: steps per launch, or per halo
+   exchange of the slab path (rounded up to even there) (0 = automatic, <= 4096),
+   and the number of workgroups per CU the 160 KiB LDS is split for
+   (0 = automatic, <= 8), which sets the tile and slab width. */
 lbm_status lbm_set_tiling(lbm_problem h, int32_t steps_per_launch, int32_t wgs_per_cu);
 
 /* Device time of the kernels of the last lbm_advance, in ms (HIP events). */
@@ -196,7 +201,7 @@ lbm_status lbm_batch_last_advance_ms(lbm_batch b, float* ms);
 
 /* Planner: 0 = automatic, 1 = force HBM streaming for every instance,
    2 = force on-chip resident (fails with UNSUPPORTED if an instance does not fit),
-   3 = force temporal blocking. */
+   3 = force temporal blocking, 4 = force slabs (see lbm_set_path). */
 lbm_status lbm_batch_set_path(lbm_batch b, int32_t path);
 
 /* Temporal blocking parameters of a batch (see lbm_set_tiling). */

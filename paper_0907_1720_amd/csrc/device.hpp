@@ -43,6 +43,17 @@ struct DevJobInst {
   int32_t pad_;
 };
 
+// Slab path: an instance split over several co-resident workgroups (one slab
+// each) that exchange halo strips every s steps; ring neighbours by index.
+struct DevSlab {
+  int32_t ti;                // index into the DevTileInst table
+  int32_t x0;                // first core node
+  int32_t core;              // core nodes (>= halo)
+  int32_t left;              // slab (workgroup) holding the nodes left of x0, periodic
+  int32_t right;             // slab holding the nodes from x0 + core on
+  int32_t pad_;
+};
+
 // Tiled path: one record per tile (workgroup) and one per instance.
 struct DevTile {
   int32_t ti;                // index into the DevTileInst table

@@ -410,6 +410,139 @@ __global__ __launch_bounds__(1024) void k_tile(const DevTile* __restrict__ tiles
 }
 
 // ---------------------------------------------------------------------------
+// Slabs: an instance too large for one workgroup's LDS is split into slabs,
+// one per workgroup of a launch small enough for all its workgroups to be
+// resident at once.  A slab holds its core and a halo of s H nodes on each
+// side in LDS for all steps of the call: every block of s steps shrinks the
+// exact region by H per step down to the core (as in the tiled path), then the
+// slab publishes the first and last `halo` nodes of its core, raises its flag,
+// waits for both ring neighbours' flags and refills its halos from their
+// strips.  State crosses HBM only at the start and the end of the call
+// (input buffer -> LDS -> other buffer).  Strips alternate between two buffers
+// by block parity: a slab overwrites a parity only after its neighbours have
+// raised the flag of the following block, i.e. after they read it.  A wait
+// that outlasts kSlabSpin polls marks the instance (status bit 2) and the
+// workgroup stops, so a scheduling fault cannot hang the GPU.
+//
+// Strips and flags move with device-scope (agent) relaxed atomic stores and
+// loads, which are coherent across the XCDs' L2 caches without whole-cache
+// write-back or invalidation; each wave waits for its strip stores to complete
+// (vmcnt 0) before the workgroup barrier that precedes the flag store, and the
+// strips are loaded only after the flag load has returned.
+// ---------------------------------------------------------------------------
+constexpr int kSlabSpin = 1 << 22;
+
+template <typename T>
+__device__ __forceinline__ void store_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T load_agent(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait until this wave's vector memory operations have completed
+__device__ __forceinline__ void wait_vm() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0) expcnt(7) lgkmcnt(15)
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <int Q, int D, int P, typename T, typename A>
+__device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const DevSlab& sl, const DevTileInst& ti,
+                              const T* __restrict__ gin, T* __restrict__ gout, int s_per, int halo,
+                              T* __restrict__ xbuf, int* __restrict__ flags, int me,
+                              const DevCoef* __restrict__ cf, int* __restrict__ status) {
+  constexpr int H = Q / 2;
+  const int B = blockDim.x;
+  const int t = threadIdx.x;
+  const int n = ti.n, stride = ti.stride;
+  const int W = sl.core + 2 * halo;
+  const int strip = Q * halo;   // values per strip
+  const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
+  for (int j = 0; j < Q; ++j)
+    for (int i = t; i < W; i += B) S[i * Q + j] = gin[(int64_t)j * stride + wrap_any(sl.x0 - halo + i, n)];
+  if (t == 0) *bail = 0;
+  __syncthreads();
+  int done = 0, sb = 0;
+  for (int blk = 0; done < ti.steps; ++blk) {
+    sb = ti.steps - done < s_per ? ti.steps - done : s_per;
+    for (int k = 0; k < sb; ++k) {
+      const int lo = k * H, hi = W - k * H;
+      if ((k & 1) == 0)
+        aa_sweep<Q, false, 1>(S, lo, hi, t, B, relax);
+      else
+        aa_sweep<Q, true, 1>(S, lo, hi, t, B, relax);
+      __syncthreads();
+    }
+    done += sb;
+    if (done >= ti.steps) break;
+    // publish [left strip | right strip] of the core (natural layout: sb = s_per is even)
+    T* mine = xbuf + ((size_t)me * 2 + (blk & 1)) * 2 * strip;
+    for (int idx = t; idx < 2 * strip; idx += B) {
+      const int side = idx / strip, r = idx - side * strip, j = r / halo, h = r - j * halo;
+      const int x = side == 0 ? halo + h : W - 2 * halo + h;
+      store_agent(mine + idx, S[x * Q + j]);
+    }
+    wait_vm();
+    __syncthreads();
+    if (t == 0) {
+      store_agent(flags + me, blk + 1);
+      int spins = 0;
+      while ((__hip_atomic_load(flags + sl.left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= blk ||
+              __hip_atomic_load(flags + sl.right, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= blk) &&
+             spins < kSlabSpin) {
+        __builtin_amdgcn_s_sleep(4);
+        ++spins;
+      }
+      if (spins >= kSlabSpin) {
+        atomicOr(status + ti.inst, 2);
+        *bail = 1;
+      }
+    }
+    __syncthreads();
+    if (*bail) break;
+    // my left halo <- the left neighbour's right strip; my right halo <- the right neighbour's left strip
+    const T* lft = xbuf + ((size_t)sl.left * 2 + (blk & 1)) * 2 * strip + strip;
+    const T* rgt = xbuf + ((size_t)sl.right * 2 + (blk & 1)) * 2 * strip;
+    for (int idx = t; idx < 2 * strip; idx += B) {
+      const int side = idx / strip, r = idx - side * strip, j = r / halo, h = r - j * halo;
+      if (side == 0)
+        S[h * Q + j] = load_agent(lft + r);
+      else
+        S[(W - halo + h) * Q + j] = load_agent(rgt + r);
+    }
+    __syncthreads();
+  }
+  bool bad = false;
+  const bool odd = (sb & 1) != 0;
+  for (int j = 0; j < Q; ++j) {
+    for (int i = halo + t; i < halo + sl.core; i += B) {
+      const T v = odd ? S[(i - velocity(j)) * Q + opposite(j)] : S[i * Q + j];
+      bad |= !__builtin_isfinite(v);
+      gout[(int64_t)j * stride + sl.x0 + (i - halo)] = v;
+    }
+  }
+  if (bad) atomicOr(status + ti.inst, 1);
+}
+
+// one instantiation per equilibrium variant (own register count, as k_resident)
+template <int Q, int D, int P, typename T, typename A>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(resident_waves_per_simd<Q, D, P, A>())))
+void k_slab(const DevSlab* __restrict__ slabs, const DevTileInst* __restrict__ tinsts, T* __restrict__ buf0,
+            T* __restrict__ buf1, int s_per, int halo, T* __restrict__ xbuf, int* __restrict__ flags,
+            const DevCoef* __restrict__ coefs, int* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* S = reinterpret_cast<T*>(smem_raw);
+  const int me = blockIdx.x;
+  const DevSlab sl = slabs[me];
+  const DevTileInst ti = tinsts[sl.ti];
+  int* bail = reinterpret_cast<int*>(smem_raw + (size_t)(sl.core + 2 * halo) * Q * sizeof(T));
+  const T* gin = (ti.cur0 ? buf1 : buf0) + ti.off;
+  T* gout = (ti.cur0 ? buf0 : buf1) + ti.off;
+  slab_instance<Q, D, P, T, A>(S, bail, sl, ti, gin, gout, s_per, halo, xbuf, flags, me, coefs + ti.inst, status);
+}
+
+// ---------------------------------------------------------------------------
 // read-outs
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -619,6 +752,50 @@ hipError_t launch_tile(int q, int prec, const DevTile* tiles, int ntiles, const 
   void* args[] = {(void*)&tiles, (void*)&tinsts, (void*)&buf0, (void*)&buf1, (void*)&launch, (void*)&s_per,
                   (void*)&halo,  (void*)&coefs,  (void*)&status};
   return hipLaunchKernel(fn, dim3(ntiles), dim3(block), args, lds, s);
+}
+
+namespace {
+template <int Q, typename T, typename A>
+const void* slab_fn(int code) {
+  switch (code) {
+#define LBM_CASE(DD, PP) \
+  case DD | (PP << 8):   \
+    return (const void*)k_slab<Q, DD, PP, T, A>;
+    LBM_VARIANT_CASES
+#undef LBM_CASE
+  }
+  return nullptr;
+}
+const void* slab_kernel(int q, int prec, int code) {
+  if (q == 5) {
+    if (prec == 0) return slab_fn<5, double, double>(code);
+    if (prec == 1) return slab_fn<5, float, double>(code);
+    return slab_fn<5, float, float>(code);
+  }
+  if (prec == 0) return slab_fn<7, double, double>(code);
+  if (prec == 1) return slab_fn<7, float, double>(code);
+  return slab_fn<7, float, float>(code);
+}
+}  // namespace
+
+hipError_t launch_slab(int q, int prec, int code, const DevSlab* slabs, int nslabs, const DevTileInst* tinsts, void* buf0,
+                       void* buf1, int s_per, int halo, void* xbuf, int* flags, const DevCoef* coefs, int* status,
+                       int block, size_t lds, hipStream_t s) {
+  const void* fn = slab_kernel(q, prec, code);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)&slabs, (void*)&tinsts, (void*)&buf0, (void*)&buf1, (void*)&s_per,
+                  (void*)&halo,  (void*)&xbuf,   (void*)&flags, (void*)&coefs, (void*)&status};
+  return hipLaunchKernel(fn, dim3(nslabs), dim3(block), args, lds, s);
+}
+
+hipError_t slab_occupancy(int q, int prec, int code, int block, size_t lds, int* blocks_per_cu) {
+  const void* fn = slab_kernel(q, prec, code);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, lds);
 }
 
 hipError_t resident_occupancy(int q, int prec, int code, int block, size_t lds, int* blocks_per_cu) {

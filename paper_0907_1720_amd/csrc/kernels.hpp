@@ -46,6 +46,12 @@ inline int variant_code(int D, int parity) { return D | (parity << 8); }
 // relaxation; 2 = FP32 deviation storage, FP32 relaxation.
 hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n, int stride,
                        const DevCoef* cf, hipStream_t s);
+// slabs: one launch no larger than the GPU holds at once, one workgroup per
+// slab; flags[0 .. nslabs) start at 0; xbuf holds 4 Q halo values per slab
+hipError_t launch_slab(int q, int prec, int code, const DevSlab* slabs, int nslabs, const DevTileInst* tinsts,
+                       void* buf0, void* buf1, int s_per, int halo, void* xbuf, int* flags, const DevCoef* coefs,
+                       int* status, int block, size_t lds, hipStream_t s);
+hipError_t slab_occupancy(int q, int prec, int code, int block, size_t lds, int* blocks_per_cu);
 // bounded domains: reset `layers` (1..32) nodes at each end from phib[0 .. 2 layers)
 // (kind 1 equilibrium, 2 non-equilibrium extrapolation); D = init degree
 hipError_t launch_bound(int q, int D, int prec, void* f, int n, int stride, int layers, int kind,

@@ -27,6 +27,7 @@ using namespace lbm;
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kMaxSlabs = 2048;       // workgroups of one cooperative slab launch
 constexpr int kMaxResidentGrid = 256 * 8;
 constexpr int kMaxLaunches = 64;      // resident launches per advance pass (one per lattice, precision, variant)
 constexpr int kAuxStreams = 8;        // concurrent lanes (resident launches, tiled groups)
@@ -121,6 +122,13 @@ struct lbm_batch_s {
   DevTile* tiles_host = nullptr;
   int tiles_cap = 0;
   DevTileInst* tinsts = nullptr;
+  DevSlab* slabs = nullptr;           // two slots of slabs_cap records
+  DevSlab* slabs_host = nullptr;
+  int slabs_cap = 0;
+  void* xbuf = nullptr;               // halo strips of the slab path
+  size_t xbuf_bytes = 0;
+  int* sflags = nullptr;              // per-slab block flags
+  int sflags_cap = 0;
   DevTileInst* tinsts_host = nullptr;
   int tile_steps = 0;                 // steps per tiled launch (0 = automatic)
   int tile_wgs = 0;                   // tiled workgroups per CU the LDS budget is split for (0 = automatic)
@@ -219,6 +227,10 @@ void destroy_batch(lbm_batch_s* b) {
   hipFree(b->tinsts);
   if (b->tiles_host) hipHostFree(b->tiles_host);
   if (b->tinsts_host) hipHostFree(b->tinsts_host);
+  hipFree(b->slabs);
+  if (b->slabs_host) hipHostFree(b->slabs_host);
+  hipFree(b->xbuf);
+  hipFree(b->sflags);
   if (b->ev0) hipEventDestroy(b->ev0);
   if (b->ev1) hipEventDestroy(b->ev1);
   for (int k = 0; k < kAuxStreams; ++k) {
@@ -483,6 +495,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   std::map<std::tuple<int, int, int>, std::vector<int>> res;   // (q == 7, prec, variant code)
   std::vector<int> str;          // one launch per step (the plain path)
   std::vector<int> til[2][3];    // temporal blocking, by (q, prec)
+  std::map<std::tuple<int, int, int>, std::vector<int>> slb;   // slabs, by (q == 7, prec, variant)
   for (int i = 0; i < count; ++i) {
     if (steps[i] == 0) continue;
     const HostInst& h = b->inst[i];
@@ -491,8 +504,10 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     if (b->path == 2 && !fits) return LBM_ERR_UNSUPPORTED;
     if (b->path == 1)
       str.push_back(i);
-    else if (b->path == 3 || !fits)
+    else if (b->path == 3)
       til[h.q == 7][h.prec].push_back(i);
+    else if (b->path == 4 || !fits)
+      slb[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D)].push_back(i);
     else
       res[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D)].push_back(i);
   }
@@ -622,6 +637,121 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   std::vector<DevTile> tvec;
   DevTileInst* htin = b->tinsts_host + (size_t)k * count;
   int tin_used = 0;
+  // slab plan per (q, prec): cooperative launches of at most `capacity` slabs
+  // (every workgroup of a launch resident at once), run one after another on
+  // one lane; an instance whose slabs exceed one launch, or whose slabs would
+  // be narrower than a halo, goes to temporal blocking instead
+  struct SlabLaunch { int q; int prec; int code; int first, count, s, halo, block; size_t lds; size_t xoff; int foff; };
+  std::vector<SlabLaunch> slaunch;
+  std::vector<DevSlab> svec;
+  size_t xbuf_need = 0;
+  int flags_need = 0;
+  int min_per_cu = 1 << 30;
+  for (const auto& group : slb) {
+    {
+      const int qq = std::get<0>(group.first), pr = std::get<1>(group.first), code = std::get<2>(group.first);
+      const std::vector<int>& g = group.second;
+      const int q = qq ? 7 : 5, H = q / 2;
+      const size_t es = pr ? sizeof(float) : sizeof(double);
+      const int wgs = b->tile_wgs > 0 ? b->tile_wgs : 2;
+      const int W = (int)((b->lim.lds_max / (size_t)wgs - 16) / (q * es));
+      int sp = b->tile_steps > 0 ? (b->tile_steps + 1) / 2 * 2 : 16;   // even: strips in natural layout
+      while (sp > 2 && W - 2 * sp * H < 2 * sp * H) sp -= 2;
+      const int halo = sp * H;
+      const int cmax = W - 2 * halo;
+      const int block = std::min(1024, std::max(64, (W / 2 + 63) / 64 * 64));
+      const size_t lds = (size_t)W * q * es + 16;
+      int per_cu = 0;
+      if (cmax < halo || slab_occupancy(q, pr, code, block, lds, &per_cu) != hipSuccess) per_cu = 0;
+      const int capacity = std::min(per_cu * b->lim.cus, kMaxSlabs);
+      if (per_cu > 0) min_per_cu = std::min(min_per_cu, per_cu);
+      SlabLaunch L{q, pr, code, (int)svec.size(), 0, sp, halo, block, lds, 0, 0};
+      for (int i : g) {
+        const HostInst& h = b->inst[i];
+        const int ks = cmax > 0 ? (h.n + cmax - 1) / cmax : 0;
+        const int core = ks > 0 ? (h.n + ks - 1) / ks : 0;
+        if (ks < 1 || ks > capacity || core < halo || h.n - (ks - 1) * core < halo) {
+          til[qq][pr].push_back(i);
+          continue;
+        }
+        if (L.count + ks > capacity) {
+          slaunch.push_back(L);
+          L.first = (int)svec.size();
+          L.count = 0;
+        }
+        DevTileInst& ti = htin[tin_used];
+        ti.off = h.off;
+        ti.n = h.n;
+        ti.stride = h.stride;
+        ti.steps = (int)steps[i];
+        ti.cur0 = h.cur;
+        ti.degree = h.D;
+        ti.inst = i;
+        for (int m = 0; m < ks; ++m) {
+          DevSlab sl;
+          sl.ti = tin_used;
+          sl.x0 = m * core;
+          sl.core = std::min(core, h.n - m * core);
+          sl.left = L.count + (m + ks - 1) % ks;
+          sl.right = L.count + (m + 1) % ks;
+          sl.pad_ = 0;
+          svec.push_back(sl);
+        }
+        L.count += ks;
+        ++tin_used;
+      }
+      if (L.count) slaunch.push_back(L);
+    }
+  }
+  // every launch its own strip and flag region (launches may run side by side)
+  for (SlabLaunch& S : slaunch) {
+    S.xoff = xbuf_need;
+    S.foff = flags_need;
+    xbuf_need += ((size_t)S.count * 4 * S.q * S.halo * (S.prec ? sizeof(float) : sizeof(double)) + 255) / 256 * 256;
+    flags_need += S.count;
+  }
+  // side by side only while all their workgroups fit the GPU twice over;
+  // otherwise one after another (each launch alone fits by construction)
+  int total_slabs = 0;
+  for (const SlabLaunch& S : slaunch) total_slabs += S.count;
+  const bool slab_side_by_side = slaunch.size() > 1 && 2 * (int64_t)total_slabs <= (int64_t)min_per_cu * b->lim.cus;
+  if (!svec.empty()) {
+    if ((int)svec.size() > b->slabs_cap || xbuf_need > b->xbuf_bytes || flags_need > b->sflags_cap) {
+      // grow the slab tables and exchange buffers; earlier passes must be done with them
+      LBM_HIP(hipStreamSynchronize(b->stream));
+      if ((int)svec.size() > b->slabs_cap) {
+        hipFree(b->slabs);
+        if (b->slabs_host) hipHostFree(b->slabs_host);
+        b->slabs = nullptr;
+        b->slabs_host = nullptr;
+        b->slabs_cap = 0;
+        const int cap = (int)svec.size() * 2;
+        if (hipMalloc(&b->slabs, sizeof(DevSlab) * 2 * cap) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+        if (hipHostMalloc((void**)&b->slabs_host, sizeof(DevSlab) * 2 * cap, hipHostMallocDefault) != hipSuccess)
+          return LBM_ERR_OUT_OF_MEMORY;
+        b->slabs_cap = cap;
+      }
+      if (xbuf_need > b->xbuf_bytes) {
+        hipFree(b->xbuf);
+        b->xbuf = nullptr;
+        b->xbuf_bytes = 0;
+        if (hipMalloc(&b->xbuf, xbuf_need) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+        b->xbuf_bytes = xbuf_need;
+      }
+      if (flags_need > b->sflags_cap) {
+        hipFree(b->sflags);
+        b->sflags = nullptr;
+        b->sflags_cap = 0;
+        if (hipMalloc(&b->sflags, sizeof(int) * flags_need) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+        b->sflags_cap = flags_need;
+      }
+    }
+    std::memcpy(b->slabs_host + (size_t)k * b->slabs_cap, svec.data(), sizeof(DevSlab) * svec.size());
+    for (const auto& group : slb) {
+      lbm_status st = ensure_second_buffer(b, std::get<1>(group.first) != 0);
+      if (st != LBM_OK) return st;
+    }
+  }
   for (int qq = 0; qq < 2; ++qq) {
     for (int pr = 0; pr < 3; ++pr) {
       const std::vector<int>& g = til[qq][pr];
@@ -698,9 +828,16 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   LBM_HIP(hipEventRecord(b->ev0, b->stream));
   if (!tvec.empty()) {
     DevTile* dt = b->tiles + (size_t)k * b->tiles_cap;
-    DevTileInst* dti = b->tinsts + (size_t)k * count;
     LBM_HIP(hipMemcpyAsync(dt, b->tiles_host + (size_t)k * b->tiles_cap, sizeof(DevTile) * tvec.size(),
                            hipMemcpyHostToDevice, b->stream));
+  }
+  if (!svec.empty()) {
+    DevSlab* ds = b->slabs + (size_t)k * b->slabs_cap;
+    LBM_HIP(hipMemcpyAsync(ds, b->slabs_host + (size_t)k * b->slabs_cap, sizeof(DevSlab) * svec.size(),
+                           hipMemcpyHostToDevice, b->stream));
+  }
+  if (tin_used) {
+    DevTileInst* dti = b->tinsts + (size_t)k * count;
     LBM_HIP(hipMemcpyAsync(dti, htin, sizeof(DevTileInst) * tin_used, hipMemcpyHostToDevice, b->stream));
   }
   DevJobInst* ditems = b->items + (size_t)k * b->items_cap;
@@ -714,7 +851,8 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   }
   // every resident launch and every tiled group is a lane on an auxiliary
   // stream; the fork is recorded after all table uploads above
-  const int lanes = (int)launches.size() + (int)tgroups.size();
+  const int lanes = (int)launches.size() + (int)tgroups.size() +
+                    (slaunch.empty() ? 0 : slab_side_by_side ? (int)slaunch.size() : 1);
   const bool fork = lanes > 1;
   if (fork) LBM_HIP(hipEventRecord(b->fork, b->stream));
   int lane = 0;
@@ -759,6 +897,32 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int L = (int)((htin[t].steps + G.s - 1) / G.s);
       h.cur = htin[t].cur0 ^ (L & 1);
     }
+  }
+  // slab launches: each needs all its workgroups resident at once.  Each fits
+  // the GPU alone, and the other lanes' kernels never wait on it, so its
+  // workgroups all get CUs once those kernels retire; two slab launches side
+  // by side could each hold CUs the other waits for, so they share a lane
+  // unless all of them fit the GPU twice over
+  if (!slaunch.empty()) {
+    const DevSlab* ds = b->slabs + (size_t)k * b->slabs_cap;
+    const DevTileInst* dti = b->tinsts + (size_t)k * count;
+    hipStream_t st = nullptr;
+    for (size_t l = 0; l < slaunch.size(); ++l) {
+      if (l == 0 || slab_side_by_side) {
+        st = lane_stream(lane);
+        if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
+        ++lane;
+      }
+      const SlabLaunch& L = slaunch[l];
+      void* b0 = L.prec ? (void*)b->f32[0] : (void*)b->f64[0];
+      void* b1 = L.prec ? (void*)b->f32[1] : (void*)b->f64[1];
+      int* flags = b->sflags + L.foff;
+      LBM_HIP(hipMemsetAsync(flags, 0, sizeof(int) * L.count, st));
+      LBM_HIP(launch_slab(L.q, L.prec, L.code, ds + L.first, L.count, dti, b0, b1, L.s, L.halo,
+                          (unsigned char*)b->xbuf + L.xoff, flags, b->coefs, b->status, L.block, L.lds, st));
+    }
+    for (const DevSlab& sl : svec)
+      if (sl.x0 == 0) b->inst[htin[sl.ti].inst].cur ^= 1;   // one flip per instance: output in the other buffer
   }
   if (fork) {
     const int nst = std::min<int>(lanes, kAuxStreams);
@@ -1181,7 +1345,7 @@ lbm_status lbm_load_f(lbm_problem h, const void* host_buf, size_t bytes) {
 }
 
 lbm_status lbm_set_path(lbm_problem h, int32_t path) {
-  if (!h || path < 0 || path > 3) return LBM_ERR_INVALID_ARG;
+  if (!h || path < 0 || path > 4) return LBM_ERR_INVALID_ARG;
   h->b->path = path;
   return LBM_OK;
 }
@@ -1233,7 +1397,7 @@ lbm_status lbm_batch_last_advance_ms(lbm_batch b, float* ms) {
 }
 
 lbm_status lbm_batch_set_path(lbm_batch b, int32_t path) {
-  if (!b || path < 0 || path > 3) return LBM_ERR_INVALID_ARG;
+  if (!b || path < 0 || path > 4) return LBM_ERR_INVALID_ARG;
   b->path = path;
   return LBM_OK;
 }

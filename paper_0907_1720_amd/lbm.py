@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmhpde.so")
 
 OK, INVALID_ARG, UNSUPPORTED, SINGULAR_TAU, OUT_OF_MEMORY, DEVICE, NONFINITE, BUSY = range(8)
-PATH_AUTO, PATH_STREAM, PATH_RESIDENT, PATH_TILED = 0, 1, 2, 3
+PATH_AUTO, PATH_STREAM, PATH_RESIDENT, PATH_TILED, PATH_SLAB = 0, 1, 2, 3, 4
 BC_PERIODIC, BC_DIRICHLET_EQ, BC_DIRICHLET_NEE = 0, 1, 2
 
 

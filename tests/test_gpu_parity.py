@@ -140,6 +140,54 @@ def test_tiled_path_bitwise_equals_resident_and_stream(n, steps, s_per, kind):
     assert rel2(outs[lbm.PATH_TILED], O.run(p, phi0, steps)) <= FP64_TOL
 
 
+# slab path: (n, steps, steps per halo exchange, workgroups per CU) chosen for 1, 2, 3, 10
+# and 16 slabs per instance (the last block of an odd step count ends in AA-odd layout)
+@pytest.mark.parametrize("n,steps,s_per,wgs", [(300, 37, 4, 2), (700, 21, 16, 8), (1000, 64, 8, 8),
+                                               (4099, 45, 16, 8)])
+@pytest.mark.parametrize("kind", ["kdv", "kawahara", "mkdv", "kdv32"])
+def test_slab_path_bitwise_equals_stream(n, steps, s_per, wgs, kind):
+    if kind in ("kdv", "kdv32"):
+        p = W.kdv(0.5, n, 0.1, 1e-4, 2.0, 0.0, prec=W.F32_DEV if kind == "kdv32" else W.F64)
+    elif kind == "mkdv":
+        p = W.mkdv(0.7, n, 0.1, 1e-4, 2.0, 0.0)
+    else:
+        p = W.kawahara(n, 0.1, 2e-5, 3.0, 0.0)
+    phi0 = _smooth_phi(n, n + 3)
+    say("case slab", kind, n, steps, s_per, wgs)
+    outs = {}
+    for path in (lbm.PATH_STREAM, lbm.PATH_SLAB):
+        s = lbm.Solver(p)
+        s.set_path(path)
+        s.set_tiling(s_per, wgs)
+        s.load_phi(phi0)
+        s.advance(steps)
+        s.advance(steps + 1)
+        outs[path] = s.read_phi()
+        s.close()
+    assert np.array_equal(outs[lbm.PATH_SLAB], outs[lbm.PATH_STREAM])
+    if kind != "kdv32":
+        assert rel2(outs[lbm.PATH_SLAB], O.run(p, phi0, 2 * steps + 1)) <= FP64_TOL
+
+
+def test_slab_path_several_cooperative_launches():
+    """More slabs than one cooperative launch holds: consecutive launches on one lane."""
+    n, count = 4099, 240                     # 10 slabs each at 8 workgroups per CU
+    probs = [W.kdv(0.5 + 0.001 * i, n, 0.1, 1e-4, 2.0, 0.0) for i in range(count)]
+    phis = [_smooth_phi(n, 100 + i) for i in range(count)]
+    outs = []
+    for path in (lbm.PATH_STREAM, lbm.PATH_SLAB):
+        b = lbm.Batch(probs)
+        b.set_path(path)
+        b.set_tiling(16, 8)
+        b.load_phi(phis)
+        b.advance(34)
+        outs.append([b.read_phi(i) for i in range(count)])
+        b.close()
+    for (a, sa), (c, sc) in zip(*outs):
+        assert sa == lbm.OK and sc == lbm.OK
+        assert np.array_equal(a, c)
+
+
 def test_resident_path_refuses_what_does_not_fit():
     p = W.kdv(0.5, 4099, 0.1, 1e-4, 2.0, 0.0)      # 5 * 4099 * 8 bytes > 160 KiB
     s = lbm.Solver(p)
