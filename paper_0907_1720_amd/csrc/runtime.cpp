@@ -27,7 +27,8 @@ using namespace lbm;
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMaxSlabs = 2048;       // workgroups of one cooperative slab launch
+constexpr int kMaxSlabs = 2048;       // workgroups of one slab launch
+constexpr int kSplitNodes = 1024;     // smallest grid split into slabs when the GPU is mostly idle
 constexpr int kMaxResidentGrid = 256 * 8;
 constexpr int kMaxLaunches = 64;      // resident launches per advance pass (one per lattice, precision, variant)
 constexpr int kAuxStreams = 8;        // concurrent lanes (resident launches, tiled groups)
@@ -495,7 +496,18 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   std::map<std::tuple<int, int, int>, std::vector<int>> res;   // (q == 7, prec, variant code)
   std::vector<int> str;          // one launch per step (the plain path)
   std::vector<int> til[2][3];    // temporal blocking, by (q, prec)
-  std::map<std::tuple<int, int, int>, std::vector<int>> slb;   // slabs, by (q == 7, prec, variant)
+  // slabs, by (q == 7, prec, variant, workgroups per CU)
+  std::map<std::tuple<int, int, int, int>, std::vector<int>> slb;
+  // A pass whose resident instances fill less than a quarter of the GPU's LDS
+  // leaves most CUs idle; its step time is that of its largest instances, one
+  // CU each.  There, instances of kSplitNodes nodes or more are split into
+  // narrow slabs (an eighth of an LDS) spread over otherwise idle CUs.
+  size_t res_bytes = 0;
+  for (int i = 0; i < count; ++i)
+    if (steps[i] && b->path == 0 && fits_resident(b, b->inst[i]))
+      res_bytes += (size_t)b->inst[i].q * b->inst[i].n * elem_size(b->inst[i]);
+  const bool latency = b->path == 0 && b->res_grid == 0 && 4 * res_bytes < (size_t)b->lim.cus * b->lim.lds_max;
+  const int slab_wgs = b->tile_wgs > 0 ? b->tile_wgs : 2;
   for (int i = 0; i < count; ++i) {
     if (steps[i] == 0) continue;
     const HostInst& h = b->inst[i];
@@ -507,7 +519,9 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     else if (b->path == 3)
       til[h.q == 7][h.prec].push_back(i);
     else if (b->path == 4 || !fits)
-      slb[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D)].push_back(i);
+      slb[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D, slab_wgs)].push_back(i);
+    else if (latency && h.n >= kSplitNodes)
+      slb[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D, 8)].push_back(i);
     else
       res[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D)].push_back(i);
   }
@@ -650,10 +664,10 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   for (const auto& group : slb) {
     {
       const int qq = std::get<0>(group.first), pr = std::get<1>(group.first), code = std::get<2>(group.first);
+      const int wgs = std::get<3>(group.first);
       const std::vector<int>& g = group.second;
       const int q = qq ? 7 : 5, H = q / 2;
       const size_t es = pr ? sizeof(float) : sizeof(double);
-      const int wgs = b->tile_wgs > 0 ? b->tile_wgs : 2;
       const int W = (int)((b->lim.lds_max / (size_t)wgs - 16) / (q * es));
       int sp = b->tile_steps > 0 ? (b->tile_steps + 1) / 2 * 2 : 16;   // even: strips in natural layout
       while (sp > 2 && W - 2 * sp * H < 2 * sp * H) sp -= 2;
