@@ -257,8 +257,10 @@ lbm_status lbm_server_submit(lbm_server s, const lbm_desc* d, const double* phi0
 
 /* One round: admit queued requests in arrival order while a slot and arena
    space are free (f := f_eq(phi0)), advance every active request by
-   min(block_steps, remaining) steps, retire finished requests (phi read out,
-   space released).  Synchronises the stream.  Counts are optional outputs. */
+   min(block_steps * r, remaining) steps, where r in [1, 8] is the cost per
+   step (lattice size x polynomial degree) of the costliest active request over
+   the request's own, retire finished requests (phi read out, space released).
+   Synchronises the stream.  Counts are optional outputs. */
 lbm_status lbm_server_step(lbm_server s, int32_t* active, int32_t* queued, int32_t* retired);
 
 /* Result of request id: LBM_OK with phi in out[0..n) (n >= the request's node

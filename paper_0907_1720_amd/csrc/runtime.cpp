@@ -1649,12 +1649,19 @@ lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int3
     sl.bytes = bytes;
   }
   sv->queue.erase(sv->queue.begin(), sv->queue.begin() + qi);
-  // one block
+  // one block.  A round lasts as long as its slowest request's block; requests
+  // whose steps cost less (lattice size x polynomial degree) take
+  // proportionally more steps in the same round, up to 8 blocks
+  auto step_cost = [&](size_t k) { return (double)b->inst[k].q * ((b->inst[k].D & 0xff) + 3); };
+  double cmax = 0.0;
+  for (size_t k = 0; k < sv->slots.size(); ++k)
+    if (sv->slots[k].active) cmax = std::max(cmax, step_cost(k));
   int act = 0;
   double nu = 0.0;
   for (size_t k = 0; k < sv->slots.size(); ++k) {
     const Slot& sl = sv->slots[k];
-    sv->steps_buf[k] = sl.active ? std::min<int64_t>(sl.remaining, sv->block) : 0;
+    const double scale = sl.active ? std::min(8.0, std::max(1.0, cmax / step_cost(k))) : 1.0;
+    sv->steps_buf[k] = sl.active ? std::min<int64_t>(sl.remaining, (int64_t)(sv->block * scale)) : 0;
     if (sl.active) {
       ++act;
       nu += (double)sv->steps_buf[k] * b->inst[k].n;
