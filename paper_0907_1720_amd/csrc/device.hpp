@@ -12,10 +12,11 @@ constexpr int kRow = 20;   // coefficient row length (max degree 19 + 1)
 // Per-problem constants on the device.
 struct DevCoef {
   double w0;                 // 1 - omega
-  double s0;                 // added to sum_j f_j: 0, or phi_rest for FP32 storage with FP64 relaxation
+  double s0;                 // added to sum_j g_j before odd tables: phi_rest (FP32 storage, FP64 relaxation)
   double phi_rest;           // rest state of the FP32 deviation storage (0 for FP64 storage)
   double cst[8];             // added after relaxation: 0, or -omega f_rest_j (FP32 storage, FP64 relaxation)
-  double wc[8][kRow];        // FP64 relaxation: omega * G[j][d] over the kept degrees (all, or odd only)
+  double wc[8][kRow];        // FP64 relaxation: omega * G[j][d] over the kept degrees (all, or odd only);
+                             // omega * H[j][d] for dense tables with FP32 deviation storage
   double init[8][kRow];      // f := f_eq(phi): G[j][d] (FP64 storage) or H[j][d] (FP32 deviations)
   float w0f;
   float pad_[3];
@@ -84,10 +85,11 @@ __host__ __device__ constexpr int opposite(int j) {
 // Storage type T, arithmetic type A; the zeroth moment is always summed in
 // FP64.  Three precisions share this code:
 //  * FP64 storage:  f*_j = w0 f_j + sum_d (omega G[j][d]) phi^d
-//  * FP32 deviations g = f - f_rest, FP64 relaxation (kRest):
-//        phi = phi_rest + sum_j g_j,
+//  * FP32 deviations g = f - f_rest, FP64 relaxation (kRest): dense tables
+//        delta = sum_j g_j,  g*_j = w0 g_j + sum_{d>=1} (omega H[j][d]) delta^d
+//    with H the Taylor shift of G to the rest state; odd tables keep their
+//    parity in phi = phi_rest + delta:
 //        g*_j = w0 g_j + sum_d (omega G[j][d]) phi^d - omega f_rest_j
-//    (for dense tables the constant -omega f_rest_j is folded into degree 0)
 //  * FP32 deviations, FP32 relaxation: delta = sum_j g_j,
 //        g*_j = w0 g_j + sum_d (omega H[j][d]) delta^d  with H the Taylor shift
 //        of G to the rest state (H[j][0] = 0)
@@ -123,7 +125,7 @@ struct Relaxer {
   const A* __restrict__ c;   // [Q][kRow]: dense, or the odd degrees compacted
   A top[Q];
   A w0;
-  double s0;
+  double s0;                 // phi_rest (odd tables with FP32 storage)
   const double* __restrict__ cst;
 
   __device__ __forceinline__ void init(const A* __restrict__ coef, A w0_, const DevCoef* __restrict__ cf) {
@@ -140,7 +142,7 @@ struct Relaxer {
 
   __device__ __forceinline__ void operator()(T (&f)[Q]) const {
     double s = (double)f[0];
-    if constexpr (kRest) s = s0 + s;
+    if constexpr (kRest && P == 1) s = s0 + s;
 #pragma unroll
     for (int j = 1; j < Q; ++j) s += (double)f[j];
     const A p = (A)s;

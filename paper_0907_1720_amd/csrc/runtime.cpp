@@ -174,11 +174,14 @@ void fill_devcoef(const HostInst& h, DevCoef* c) {
       }
     }
     if (h.prec == LBM_F32_DEV) {
+      // odd tables: Horner in phi = phi_rest + delta, then -omega f_rest;
+      // dense tables: omega * H, the Taylor shift to the rest state, in delta
+      // itself (no cancellation against f_rest, one add less per node)
       c->s0 = m.phi_rest;
       for (int j = 0; j < m.q; ++j) {
         c->cst[j] = -m.wfrest[j];
-        // dense tables absorb the rest-state constant into the degree-0 coefficient
-        if (parity == 0) c->wc[j][0] = m.wG0rest[j];
+        if (parity == 0)
+          for (int d = 0; d <= m.D; ++d) c->wc[j][d] = m.wH[j][d];
       }
     }
   } else {
