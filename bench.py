@@ -14,8 +14,12 @@ Reported:
   roofline              the dominant kernel (the persistent LDS-resident batch
                         kernel) against the VALU peak, timed with HIP events on
                         the launch stream
+  large_grids           device rate of the workloads whose grids exceed one
+                        workgroup's LDS (slabs over co-resident workgroups):
+                        Kuramoto-Sivashinsky N = 8192 and Kawahara / K(2,2)
   serving               p50/p99 latency and throughput of a Poisson stream of
                         mixed solve requests through the continuous-batching server
+  autotune              the planner settings the autotuner kept for each batch
   cpu_baseline          the CPU oracle on a sample of the same instances
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -117,6 +121,8 @@ def main():
                     help="copy 1 GiB device to device first (reference kernel for HBM counters)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the planner's automatic settings instead of autotuning the batch first")
+    ap.add_argument("--large-only", action="store_true",
+                    help="time only the large-grid workloads (for profiler runs); prints a reduced line")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the FP32 batch (for profiler runs); prints a reduced line")
     args = ap.parse_args()
@@ -169,6 +175,29 @@ def main():
                 "nu_per_s": nu_pass * args.steps / wall, "status_ok": all(s == lbm.OK for s in st),
                 "tuning": tuning}
 
+    def large(insts, steps):
+        """Device rate of one pass over instances too large for one workgroup's LDS."""
+        b = lbm.Batch([x.problem for x in insts], stream=stream.cuda_stream)
+        b.load_phi([x.phi0 for x in insts])
+        b.advance(16)
+        torch.cuda.synchronize()
+        b.advance(steps)
+        ms = b.last_advance_ms()
+        st = all(b.read_phi(i)[1] == lbm.OK for i in (0, len(insts) - 1))
+        b.close()
+        return {"node_updates_per_s": sum(x.problem.n for x in insts) * steps / (ms * 1e-3), "kernel_ms": ms,
+                "instances": len(insts), "steps": steps, "status_ok": st}
+
+    def large_grids():
+        out = {}
+        for prec, tag in ((W.F64, "fp64"), (W.F32_DEV, "fp32")):
+            out[f"ks_n8192_{tag}"] = large([W.config3_instance(8192, i, prec=prec) for i in range(256)], 640)
+            out[f"kawahara_k22_{tag}"] = large([W.config4_instance(i, prec=prec) for i in range(512)], 500)
+        return out
+
+    if args.large_only:
+        print(json.dumps({"metric": "lattice-node updates/s (large grids only)", "large_grids": large_grids()}))
+        return
     r32 = run(W.F32_DEV)
     if args.batch_only:
         print(json.dumps({"metric": "lattice-node updates/s (FP32 batch only)", "value": r32["nu_per_s"],
@@ -176,6 +205,7 @@ def main():
                           "kernel_ms": r32["kernel_ms"], "status_ok": r32["status_ok"]}))
         return
     r64 = run(W.F64)
+    lg = large_grids()
 
     # plain FP64 path: one instance at a time, one launch per step
     sample = np.linspace(0, args.count - 1, args.plain_sample).astype(int)
@@ -240,6 +270,9 @@ def main():
                        "path": "one fused collide+stream launch per step (64-step blocks replayed from a HIP graph), "
                                "one instance at a time"},
         "speedup_vs_plain_fp64": r32["nu_per_s"] / plain,
+        "large_grids": {"workload": "Kuramoto-Sivashinsky N = 8192 (256 instances, 640 steps) and "
+                                    "Kawahara/K(2,2) N in {2048, 16384} (512 instances, 500 steps), device time",
+                        **lg},
         "status_ok": bool(r32["status_ok"] and r64["status_ok"]),
         "roofline": roofline,
         "serving": {"requests": srv_out["requests"], "arrival_rate_per_s": srv_out["rate_per_s"],
