@@ -14,6 +14,8 @@ Reported:
   roofline              the dominant kernel (the persistent LDS-resident batch
                         kernel) against the VALU peak, timed with HIP events on
                         the launch stream
+  hbm_stream            the fused collide+stream path on a 2^25-node grid:
+                        algorithmic HBM GB/s against 8 TB/s and a device copy
   large_grids           device rate of the workloads whose grids exceed one
                         workgroup's LDS (slabs over co-resident workgroups):
                         Kuramoto-Sivashinsky N = 8192 and Kawahara / K(2,2)
@@ -121,6 +123,8 @@ def main():
                     help="copy 1 GiB device to device first (reference kernel for HBM counters)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the planner's automatic settings instead of autotuning the batch first")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="time only the HBM-streaming path on one large grid (for profiler runs)")
     ap.add_argument("--large-only", action="store_true",
                     help="time only the large-grid workloads (for profiler runs); prints a reduced line")
     ap.add_argument("--batch-only", action="store_true",
@@ -195,6 +199,41 @@ def main():
             out[f"kawahara_k22_{tag}"] = large([W.config4_instance(i, prec=prec) for i in range(512)], 500)
         return out
 
+    def hbm_stream():
+        """The plain fused collide+stream path on one grid far larger than the caches
+        (2^25 nodes: 1.34 GB per FP64 buffer), against HBM peak and a device copy."""
+        out = {}
+        n, steps = 1 << 25, 128
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        out["copy_gb_per_s"] = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del src, dst
+        x = -20.0 + 40.0 / n * np.arange(n)
+        for prec, tag, es in ((W.F64, "fp64", 8), (W.F32_DEV, "fp32", 4)):
+            p = W.kdv(1.0, n, 40.0 / n, 0.05 * (40.0 / n) ** 3, 2.0, -20.0, prec=prec)
+            s = lbm.Solver(p, stream=stream.cuda_stream)
+            s.set_path(lbm.PATH_STREAM)
+            s.load_phi(W.kdv_soliton(x, 0.0, 1.0, 1.0, -5.0, period=40.0))
+            s.advance(steps)
+            torch.cuda.synchronize()
+            s.advance(steps)
+            ms = s.last_advance_ms()
+            nbytes = 2 * p.lattice() * es * n * steps
+            out[tag] = {"node_updates_per_s": n * steps / (ms * 1e-3), "algorithmic_gb_per_s": nbytes / (ms * 1e-3) / 1e9,
+                        "frac_of_8tb": nbytes / (ms * 1e-3) / 8e12, "kernel_ms": ms, "nodes": n, "steps": steps}
+            s.close()
+        return out
+
+    if args.stream_only:
+        print(json.dumps({"metric": "HBM streaming path", "hbm_stream": hbm_stream()}))
+        return
     if args.large_only:
         print(json.dumps({"metric": "lattice-node updates/s (large grids only)", "large_grids": large_grids()}))
         return
@@ -206,6 +245,7 @@ def main():
         return
     r64 = run(W.F64)
     lg = large_grids()
+    hs = hbm_stream()
 
     # plain FP64 path: one instance at a time, one launch per step
     sample = np.linspace(0, args.count - 1, args.plain_sample).astype(int)
@@ -270,6 +310,8 @@ def main():
                        "path": "one fused collide+stream launch per step (64-step blocks replayed from a HIP graph), "
                                "one instance at a time"},
         "speedup_vs_plain_fp64": r32["nu_per_s"] / plain,
+        "hbm_stream": {"workload": "one periodic KdV grid of 2^25 nodes, 128 steps on the plain fused "
+                                   "collide+stream path; algorithmic bytes 2 q s per node update", **hs},
         "large_grids": {"workload": "Kuramoto-Sivashinsky N = 8192 (256 instances, 640 steps) and "
                                     "Kawahara/K(2,2) N in {2048, 16384} (512 instances, 500 steps), device time",
                         **lg},
