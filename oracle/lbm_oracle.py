@@ -43,7 +43,7 @@ Readings where the paper is silent or inconsistent (all selectable):
 from __future__ import annotations
 
 from fractions import Fraction
-from math import comb
+from math import comb, gcd
 from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
@@ -140,7 +140,19 @@ def relaxation_taus(tau) -> Dict[int, Fraction]:
 # Sec. III: velocity sets and the printed inverse moment matrices
 # ---------------------------------------------------------------------------
 
+# D1Q5 / D1Q7: rest velocity first (Sec. III.A/B)
 VELOCITIES = (0, 1, -1, 2, -2, 3, -3)
+# D1Q4 / D1Q6 carry no rest velocity (Sec. III, opening paragraph)
+VELOCITIES_NO_REST = (1, -1, 2, -2, 3, -3)
+
+
+def lattice_velocities(q: int):
+    """e_j of D1Q<q>, j = 0..q-1."""
+    if q in (5, 7):
+        return VELOCITIES[:q]
+    if q in (4, 6):
+        return VELOCITIES_NO_REST[:q]
+    raise ValueError(f"no D1Q{q} lattice")
 
 # M_5^{-1} = (1/24) * integer matrix (Sec. III.A)
 M5_INV_DEN = 24
@@ -165,17 +177,60 @@ M7_INV_INT = (
 )
 
 
-def inverse_moment_matrix(q: int):
-    """(integer matrix, denominator) of M_q^{-1} as printed."""
+def moment_matrix_exact(q: int):
+    """M_q[k][j] = e_j^k, k, j = 0..q-1: the moment conditions sum_j e_j^k f_eq_j
+    = Pi_bar_k as a linear system (Sec. III.A/B)."""
+    e = lattice_velocities(q)
+    return [[Fraction(ej) ** k for ej in e] for k in range(q)]
+
+
+def invert_exact(M):
+    """Inverse of a square Fraction matrix by textbook Gauss-Jordan elimination
+    (exact: no rounding, so no pivoting strategy matters beyond a nonzero pivot)."""
+    q = len(M)
+    a = [list(row) + [Fraction(int(i == r)) for i in range(q)] for r, row in enumerate(M)]
+    for col in range(q):
+        piv = next(r for r in range(col, q) if a[r][col] != 0)
+        a[col], a[piv] = a[piv], a[col]
+        p = a[col][col]
+        a[col] = [v / p for v in a[col]]
+        for r in range(q):
+            if r != col and a[r][col] != 0:
+                fac = a[r][col]
+                a[r] = [v - fac * w for v, w in zip(a[r], a[col])]
+    return [row[q:] for row in a]
+
+
+def _derived_inverse(q: int):
+    """M_q^{-1} for D1Q4 / D1Q6, for which the paper prints no matrix: the exact
+    inverse written as (integer matrix, common denominator)."""
+    inv = invert_exact(moment_matrix_exact(q))
+    den = 1
+    for row in inv:
+        for v in row:
+            den = den * v.denominator // gcd(den, v.denominator)
+    return tuple(tuple(int(v * den) for v in row) for row in inv), den
+
+
+def _inverse_parts(q: int):
     if q == 5:
-        return np.array(M5_INV_INT, dtype=np.float64), float(M5_INV_DEN)
+        return M5_INV_INT, M5_INV_DEN
     if q == 7:
-        return np.array(M7_INV_INT, dtype=np.float64), float(M7_INV_DEN)
-    raise ValueError("only D1Q5 and D1Q7 are defined in the paper")
+        return M7_INV_INT, M7_INV_DEN
+    if q in (4, 6):
+        return _derived_inverse(q)
+    raise ValueError(f"no D1Q{q} lattice")
+
+
+def inverse_moment_matrix(q: int):
+    """(integer matrix, denominator) of M_q^{-1}: as printed for D1Q5 / D1Q7,
+    derived exactly for D1Q4 / D1Q6."""
+    ints, den = _inverse_parts(q)
+    return np.array(ints, dtype=np.float64), float(den)
 
 
 def inverse_moment_matrix_exact(q: int):
-    ints, den = (M5_INV_INT, M5_INV_DEN) if q == 5 else (M7_INV_INT, M7_INV_DEN)
+    ints, den = _inverse_parts(q)
     return [[Fraction(v, den) for v in row] for row in ints]
 
 
@@ -213,12 +268,12 @@ def build_model(problem) -> OracleModel:
     mdl = OracleModel()
     m = problem.order()
     q = problem.q if problem.q else (5 if m <= 4 else 7)
-    if q not in (5, 7) or q < m + 1:
+    if q not in (4, 5, 6, 7) or q < m + 1:
         raise ValueError(f"lattice D1Q{q} cannot carry an order-{m} equation (needs q >= m + 1)")
     if not problem.tau > 0.5:
         raise ValueError("tau must exceed 1/2")
     mdl.q, mdl.m = q, m
-    mdl.e = np.array(VELOCITIES[:q], dtype=np.int64)
+    mdl.e = np.array(lattice_velocities(q), dtype=np.int64)
     mdl.tau = float(problem.tau)
     mdl.scheme = int(problem.scheme)
     dx, dt = Fraction(problem.dx), Fraction(problem.dt)

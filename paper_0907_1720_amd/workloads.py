@@ -116,6 +116,14 @@ def kawahara(n, dx, dt, tau, x0, **kw) -> Problem:
                    n, dx, dt, tau, x0=x0, name="kawahara", **kw)
 
 
+def dissipative_fifth_order(nu, delta, mu, eps, n, dx, dt, tau, x0, **kw) -> Problem:
+    """phi_t + phi phi_x - nu phi_xx + delta phi_xxx + mu phi_xxxx + eps phi_xxxxx = 0
+    (m = 5; with enough diffusion nu it runs stably on D1Q6)."""
+    return Problem(_alpha(a2=-nu, a3=delta, a4=mu, a5=eps),
+                   _pis(p1=(0, 0, 0.5), p2=(0, 1), p3=(0, 1), p4=(0, 1), p5=(0, 1)),
+                   n, dx, dt, tau, x0=x0, name="dissipative5", **kw)
+
+
 def k22(n, dx, dt, tau, x0, **kw) -> Problem:
     """K(2,2): phi_t + (phi^2)_x + (phi^2)_xxx = 0: Pi_1 = Pi_3 = phi^2."""
     return Problem(_alpha(a3=1.0), _pis(p1=(0, 0, 1.0), p3=(0, 0, 1.0)), n, dx, dt, tau,
