@@ -19,7 +19,12 @@
 
 namespace lbm {
 
-const int kVelocity[kMaxQ] = {0, 1, -1, 2, -2, 3, -3};
+// Odd q puts the rest velocity first; even q (D1Q4, D1Q6, Sec. III) has none.
+int lattice_velocity(int q, int j) {
+  static const int odd[kMaxQ] = {0, 1, -1, 2, -2, 3, -3};
+  static const int even[kMaxQ] = {1, -1, 2, -2, 3, -3, 0};
+  return (q & 1) ? odd[j] : even[j];
+}
 
 namespace {
 
@@ -110,7 +115,7 @@ bool invert_moment_matrix(int q, qf inv[kMaxQ][kMaxQ]) {
   for (int k = 0; k < q; ++k) {
     for (int j = 0; j < q; ++j) {
       qf v = 1;
-      for (int p = 0; p < k; ++p) v *= kVelocity[j];
+      for (int p = 0; p < k; ++p) v *= lattice_velocity(q, j);
       a[k][j] = v;
       a[k][q + j] = (k == j) ? 1 : 0;
     }
@@ -156,7 +161,7 @@ int resolved_lattice(const lbm_desc& d) {
   int m = resolved_order(d);
   if (m == 0) return 0;
   if (d.q == 0) return m <= 4 ? 5 : 7;
-  if ((d.q != 5 && d.q != 7) || d.q < m + 1) return 0;
+  if (d.q < 4 || d.q > 7 || d.q < m + 1) return 0;
   return d.q;
 }
 
@@ -216,7 +221,7 @@ lbm_status build_model(const lbm_desc& d, Model* out) {
   const qf t2 = tk[2], t3 = tk[3], t4 = tk[4], t5 = tk[5], t6 = tk[6];
   const bool corrected = d.am == LBM_AM_CORRECTED;
   qf A[7] = {0};
-  {
+  if (q > 4) {
     qf num = t2 * (3 * t3 - t2 * t2) * beta[2] * beta[2];
     if (num != 0) {
       if (qabs(t4) < kSingular) return LBM_ERR_SINGULAR_TAU;
@@ -354,7 +359,7 @@ long double spectral_radius(const Model& m, const long double* w, long double ka
   const int q = m.q;
   const long double omega = 1.0L / (long double)m.tau, c = 1.0L - omega;
   cld E[kMaxQ], P[kMaxQ + 1], T[kMaxQ + 1], r[kMaxQ];
-  for (int j = 0; j < q; ++j) E[j] = std::polar(1.0L, -kappa * kVelocity[j]);
+  for (int j = 0; j < q; ++j) E[j] = std::polar(1.0L, -kappa * (long double)lattice_velocity(q, j));
   for (int j = 0; j < q; ++j) r[j] = c * E[j];
   poly_from_roots(r, q, P);
   for (int j = 0; j < q; ++j) {

@@ -48,7 +48,7 @@ void set_rest_state(Model* mdl, double phi_rest);
 int resolved_order(const lbm_desc& d);
 int resolved_lattice(const lbm_desc& d);
 
-extern const int kVelocity[kMaxQ];
+int lattice_velocity(int q, int j);   // e_j of D1Q<q>
 
 // Largest |eigenvalue| over Fourier modes kappa in (0, pi] of the scheme
 // linearised about uniform states phi_bar in [phi_min, phi_max] (5 states,

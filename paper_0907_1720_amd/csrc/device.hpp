@@ -72,12 +72,19 @@ struct DevTileInst {
   int32_t inst;              // index into coefficients / status
 };
 
+// Lattice velocities e_j in units of c.  Odd q (D1Q5, D1Q7) has the rest
+// velocity first: e = (0, 1, -1, 2, -2, 3, -3); even q (D1Q4, D1Q6) has none:
+// e = (1, -1, 2, -2, 3, -3).  Either way max |e_j| = q / 2.
+template <int Q>
 __host__ __device__ constexpr int velocity(int j) {
-  return j == 0 ? 0 : ((j & 1) ? (j + 1) / 2 : -(j / 2));
+  if constexpr (Q % 2 == 1) return j == 0 ? 0 : ((j & 1) ? (j + 1) / 2 : -(j / 2));
+  else return (j & 1) ? -(j / 2 + 1) : (j / 2 + 1);
 }
 // population with the opposite velocity
+template <int Q>
 __host__ __device__ constexpr int opposite(int j) {
-  return j == 0 ? 0 : ((j & 1) ? j + 1 : j - 1);
+  if constexpr (Q % 2 == 1) return j == 0 ? 0 : ((j & 1) ? j + 1 : j - 1);
+  else return j ^ 1;
 }
 
 // ---- a1 + a2 + a3 + a4: phi = sum_j f_j, f_eq_j(phi) by Horner, BGK ----

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ fin, T* __
   relax(f);
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    int y = x + velocity(j);
+    int y = x + velocity<Q>(j);
     y += (y < 0) ? n : 0;
     y -= (y >= n) ? n : 0;
     fout[(int64_t)j * stride + y] = f[j];
@@ -91,9 +91,9 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ fin, T* __
 
 // ---------------------------------------------------------------------------
 // In-LDS time steps with the alternating (AA) access pattern.  LDS holds node
-// x's populations together (S[x Q + j]; odd Q keeps lane strides free of bank
-// conflicts and every population of a node is an immediate offset from one
-// address).
+// x's populations together (S[x Q + j]; every population of a node is an
+// immediate offset from one address, and the odd strides of D1Q5 and D1Q7 keep
+// lanes free of bank conflicts -- D1Q4 and D1Q6 pay some).
 //   even step: node x reads S[x][j], writes f*_j to S[x][opp(j)]
 //   odd step:  node x reads S[x - e_j][opp(j)], writes f*_j to S[x + e_j][j]
 // Each node reads exactly the slots it writes, so one barrier per step
@@ -116,7 +116,7 @@ __device__ __forceinline__ void aa_even(T* __restrict__ S, int x, const R& r) {
   for (int j = 0; j < Q; ++j) f[j] = p[j];
   r(f);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) p[opposite(j)] = f[j];
+  for (int j = 0; j < Q; ++j) p[opposite<Q>(j)] = f[j];
 }
 
 template <int Q, typename T, typename R>
@@ -133,8 +133,8 @@ __device__ __forceinline__ void aa_even2(T* __restrict__ S, int x, int y, const 
   r(h);
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    p[opposite(j)] = f[j];
-    q[opposite(j)] = h[j];
+    p[opposite<Q>(j)] = f[j];
+    q[opposite<Q>(j)] = h[j];
   }
 }
 
@@ -144,10 +144,10 @@ __device__ __forceinline__ void aa_odd(T* __restrict__ S, int x, const R& r) {
   T* p = S + (x - H) * Q;
   T f[Q];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) f[j] = p[(H - velocity(j)) * Q + opposite(j)];
+  for (int j = 0; j < Q; ++j) f[j] = p[(H - velocity<Q>(j)) * Q + opposite<Q>(j)];
   r(f);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) p[(H + velocity(j)) * Q + j] = f[j];
+  for (int j = 0; j < Q; ++j) p[(H + velocity<Q>(j)) * Q + j] = f[j];
 }
 
 template <int Q, typename T, typename R>
@@ -158,15 +158,15 @@ __device__ __forceinline__ void aa_odd2(T* __restrict__ S, int x, int y, const R
   T f[Q], h[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    f[j] = p[(H - velocity(j)) * Q + opposite(j)];
-    h[j] = q[(H - velocity(j)) * Q + opposite(j)];
+    f[j] = p[(H - velocity<Q>(j)) * Q + opposite<Q>(j)];
+    h[j] = q[(H - velocity<Q>(j)) * Q + opposite<Q>(j)];
   }
   r(f);
   r(h);
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    p[(H + velocity(j)) * Q + j] = f[j];
-    q[(H + velocity(j)) * Q + j] = h[j];
+    p[(H + velocity<Q>(j)) * Q + j] = f[j];
+    q[(H + velocity<Q>(j)) * Q + j] = h[j];
   }
 }
 
@@ -175,10 +175,10 @@ template <int Q, typename T, typename R>
 __device__ __forceinline__ void aa_odd_wrap(T* __restrict__ S, int x, int n, const R& r) {
   T f[Q];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) f[j] = S[wrapn(x - velocity(j), n) * Q + opposite(j)];
+  for (int j = 0; j < Q; ++j) f[j] = S[wrapn(x - velocity<Q>(j), n) * Q + opposite<Q>(j)];
   r(f);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) S[wrapn(x + velocity(j), n) * Q + j] = f[j];
+  for (int j = 0; j < Q; ++j) S[wrapn(x + velocity<Q>(j), n) * Q + j] = f[j];
 }
 
 // every node x = lo + t + k B below hi, U (1 or 2) per iteration: two give
@@ -243,7 +243,7 @@ __device__ void resident_job(T* __restrict__ L, int steps, const DevJobInst& ji,
     const bool odd = (steps & 1) != 0;
     for (int j = 0; j < Q; ++j) {
       for (int x = t; x < n; x += nt) {
-        const T v = odd ? S[wrapn(x - velocity(j), n) * Q + opposite(j)] : S[x * Q + j];
+        const T v = odd ? S[wrapn(x - velocity<Q>(j), n) * Q + opposite<Q>(j)] : S[x * Q + j];
         bad |= !__builtin_isfinite(v);
         g[(int64_t)j * ji.stride + x] = v;
       }
@@ -269,7 +269,7 @@ __device__ void resident_job(T* __restrict__ L, int steps, const DevJobInst& ji,
 template <int Q, int D, int P, typename A>
 constexpr int resident_waves_per_simd() {
   if constexpr (sizeof(A) == 4) return 8;
-  if constexpr (Q == 5) return (P ? D <= 9 : D <= 5) ? 8 : 1;
+  if constexpr (Q <= 5) return (P ? D <= 9 : D <= 5) ? 8 : 1;
   return 1;
 }
 
@@ -371,7 +371,7 @@ __device__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* _
   const bool odd = (steps & 1) != 0;
   for (int j = 0; j < Q; ++j) {
     for (int i = halo + t; i < halo + core; i += B) {
-      const T v = odd ? S[(i - velocity(j)) * Q + opposite(j)] : S[i * Q + j];
+      const T v = odd ? S[(i - velocity<Q>(j)) * Q + opposite<Q>(j)] : S[i * Q + j];
       bad |= !__builtin_isfinite(v);
       gout[(int64_t)j * stride + x0 + (i - halo)] = v;
     }
@@ -517,7 +517,7 @@ __device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const D
   const bool odd = (sb & 1) != 0;
   for (int j = 0; j < Q; ++j) {
     for (int i = halo + t; i < halo + sl.core; i += B) {
-      const T v = odd ? S[(i - velocity(j)) * Q + opposite(j)] : S[i * Q + j];
+      const T v = odd ? S[(i - velocity<Q>(j)) * Q + opposite<Q>(j)] : S[i * Q + j];
       bad |= !__builtin_isfinite(v);
       gout[(int64_t)j * stride + sl.x0 + (i - halo)] = v;
     }
@@ -631,25 +631,42 @@ const void* resident_fn(int code) {
   return nullptr;
 }
 
+template <int Q>
+const void* resident_prec(int prec, int code) {
+  if (prec == 0) return resident_fn<Q, double, double>(code);
+  if (prec == 1) return resident_fn<Q, float, double>(code);
+  return resident_fn<Q, float, float>(code);
+}
+
 const void* resident_kernel(int q, int prec, int code) {
-  if (q == 5) {
-    if (prec == 0) return resident_fn<5, double, double>(code);
-    if (prec == 1) return resident_fn<5, float, double>(code);
-    return resident_fn<5, float, float>(code);
+  switch (q) {
+    case 4: return resident_prec<4>(prec, code);
+    case 5: return resident_prec<5>(prec, code);
+    case 6: return resident_prec<6>(prec, code);
+    case 7: return resident_prec<7>(prec, code);
   }
-  if (prec == 0) return resident_fn<7, double, double>(code);
-  if (prec == 1) return resident_fn<7, float, double>(code);
-  return resident_fn<7, float, float>(code);
+  return nullptr;
+}
+}  // namespace
+
+namespace {
+template <int Q>
+hipError_t launch_init_p(int D, int prec, const double* phi, void* f, int n, int stride, const DevCoef* cf,
+                         hipStream_t s) {
+  if (prec == 0) return launch_init_q<Q, double>(D, phi, (double*)f, n, stride, cf, s);
+  return launch_init_q<Q, float>(D, phi, (float*)f, n, stride, cf, s);
 }
 }  // namespace
 
 hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n, int stride,
                        const DevCoef* cf, hipStream_t s) {
-  if (prec == 0)
-    return q == 5 ? launch_init_q<5, double>(D, phi, (double*)f, n, stride, cf, s)
-                  : launch_init_q<7, double>(D, phi, (double*)f, n, stride, cf, s);
-  return q == 5 ? launch_init_q<5, float>(D, phi, (float*)f, n, stride, cf, s)
-                : launch_init_q<7, float>(D, phi, (float*)f, n, stride, cf, s);
+  switch (q) {
+    case 4: return launch_init_p<4>(D, prec, phi, f, n, stride, cf, s);
+    case 5: return launch_init_p<5>(D, prec, phi, f, n, stride, cf, s);
+    case 6: return launch_init_p<6>(D, prec, phi, f, n, stride, cf, s);
+    case 7: return launch_init_p<7>(D, prec, phi, f, n, stride, cf, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 namespace {
@@ -666,40 +683,62 @@ hipError_t launch_bound_q(int D, T* f, int n, int stride, int layers, int kind, 
   }
   return hipErrorInvalidValue;
 }
+
+template <int Q>
+hipError_t launch_bound_p(int D, int prec, void* f, int n, int stride, int layers, int kind, const double* phib,
+                          const DevCoef* cf, hipStream_t s) {
+  if (prec == 0) return launch_bound_q<Q, double>(D, (double*)f, n, stride, layers, kind, phib, cf, s);
+  return launch_bound_q<Q, float>(D, (float*)f, n, stride, layers, kind, phib, cf, s);
+}
+
+template <int Q>
+hipError_t launch_stream_p(int D, int prec, const void* fin, void* fout, int n, int stride, const DevCoef* cf,
+                           hipStream_t s) {
+  if (prec == 0) return launch_stream_q<Q, double, double>(D, (const double*)fin, (double*)fout, n, stride, cf, s);
+  if (prec == 1) return launch_stream_q<Q, float, double>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
+  return launch_stream_q<Q, float, float>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
+}
+
+template <int Q>
+const void* stream_prec(int prec, int code) {
+  if (prec == 0) return stream_fn<Q, double, double>(code);
+  if (prec == 1) return stream_fn<Q, float, double>(code);
+  return stream_fn<Q, float, float>(code);
+}
 }  // namespace
 
 hipError_t launch_bound(int q, int D, int prec, void* f, int n, int stride, int layers, int kind,
                         const double* phib, const DevCoef* cf, hipStream_t s) {
   if (layers < 1 || 2 * layers > 64) return hipErrorInvalidValue;
-  if (prec == 0)
-    return q == 5 ? launch_bound_q<5, double>(D, (double*)f, n, stride, layers, kind, phib, cf, s)
-                  : launch_bound_q<7, double>(D, (double*)f, n, stride, layers, kind, phib, cf, s);
-  return q == 5 ? launch_bound_q<5, float>(D, (float*)f, n, stride, layers, kind, phib, cf, s)
-                : launch_bound_q<7, float>(D, (float*)f, n, stride, layers, kind, phib, cf, s);
+  switch (q) {
+    case 4: return launch_bound_p<4>(D, prec, f, n, stride, layers, kind, phib, cf, s);
+    case 5: return launch_bound_p<5>(D, prec, f, n, stride, layers, kind, phib, cf, s);
+    case 6: return launch_bound_p<6>(D, prec, f, n, stride, layers, kind, phib, cf, s);
+    case 7: return launch_bound_p<7>(D, prec, f, n, stride, layers, kind, phib, cf, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_stream(int q, int D, int prec, const void* fin, void* fout, int n, int stride,
                          const DevCoef* cf, hipStream_t s) {
   // D carries the variant code (degree | parity << 8)
-  if (prec == 0)
-    return q == 5 ? launch_stream_q<5, double, double>(D, (const double*)fin, (double*)fout, n, stride, cf, s)
-                  : launch_stream_q<7, double, double>(D, (const double*)fin, (double*)fout, n, stride, cf, s);
-  if (prec == 1)
-    return q == 5 ? launch_stream_q<5, float, double>(D, (const float*)fin, (float*)fout, n, stride, cf, s)
-                  : launch_stream_q<7, float, double>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
-  return q == 5 ? launch_stream_q<5, float, float>(D, (const float*)fin, (float*)fout, n, stride, cf, s)
-                : launch_stream_q<7, float, float>(D, (const float*)fin, (float*)fout, n, stride, cf, s);
+  switch (q) {
+    case 4: return launch_stream_p<4>(D, prec, fin, fout, n, stride, cf, s);
+    case 5: return launch_stream_p<5>(D, prec, fin, fout, n, stride, cf, s);
+    case 6: return launch_stream_p<6>(D, prec, fin, fout, n, stride, cf, s);
+    case 7: return launch_stream_p<7>(D, prec, fin, fout, n, stride, cf, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 const void* stream_kernel(int q, int code, int prec) {
-  if (q == 5) {
-    if (prec == 0) return stream_fn<5, double, double>(code);
-    if (prec == 1) return stream_fn<5, float, double>(code);
-    return stream_fn<5, float, float>(code);
+  switch (q) {
+    case 4: return stream_prec<4>(prec, code);
+    case 5: return stream_prec<5>(prec, code);
+    case 6: return stream_prec<6>(prec, code);
+    case 7: return stream_prec<7>(prec, code);
   }
-  if (prec == 0) return stream_fn<7, double, double>(code);
-  if (prec == 1) return stream_fn<7, float, double>(code);
-  return stream_fn<7, float, float>(code);
+  return nullptr;
 }
 
 hipError_t launch_resident(int q, int prec, int code, const DevJob* jobs, const DevJobInst* jinst, int njobs,
@@ -731,15 +770,20 @@ size_t resident_static_lds(int q, int prec, int code) {
 namespace {
 template <int Q, typename T, typename A>
 const void* tile_fn() { return (const void*)k_tile<Q, T, A>; }
+template <int Q>
+const void* tile_prec(int prec) {
+  if (prec == 0) return tile_fn<Q, double, double>();
+  if (prec == 1) return tile_fn<Q, float, double>();
+  return tile_fn<Q, float, float>();
+}
 const void* tile_kernel(int q, int prec) {
-  if (q == 5) {
-    if (prec == 0) return tile_fn<5, double, double>();
-    if (prec == 1) return tile_fn<5, float, double>();
-    return tile_fn<5, float, float>();
+  switch (q) {
+    case 4: return tile_prec<4>(prec);
+    case 5: return tile_prec<5>(prec);
+    case 6: return tile_prec<6>(prec);
+    case 7: return tile_prec<7>(prec);
   }
-  if (prec == 0) return tile_fn<7, double, double>();
-  if (prec == 1) return tile_fn<7, float, double>();
-  return tile_fn<7, float, float>();
+  return nullptr;
 }
 }  // namespace
 
@@ -747,6 +791,7 @@ hipError_t launch_tile(int q, int prec, const DevTile* tiles, int ntiles, const 
                        void* buf1, int launch, int s_per, int halo, const DevCoef* coefs, int* status, int block,
                        size_t lds, hipStream_t s) {
   const void* fn = tile_kernel(q, prec);
+  if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   void* args[] = {(void*)&tiles, (void*)&tinsts, (void*)&buf0, (void*)&buf1, (void*)&launch, (void*)&s_per,
@@ -766,15 +811,20 @@ const void* slab_fn(int code) {
   }
   return nullptr;
 }
+template <int Q>
+const void* slab_prec(int prec, int code) {
+  if (prec == 0) return slab_fn<Q, double, double>(code);
+  if (prec == 1) return slab_fn<Q, float, double>(code);
+  return slab_fn<Q, float, float>(code);
+}
 const void* slab_kernel(int q, int prec, int code) {
-  if (q == 5) {
-    if (prec == 0) return slab_fn<5, double, double>(code);
-    if (prec == 1) return slab_fn<5, float, double>(code);
-    return slab_fn<5, float, float>(code);
+  switch (q) {
+    case 4: return slab_prec<4>(prec, code);
+    case 5: return slab_prec<5>(prec, code);
+    case 6: return slab_prec<6>(prec, code);
+    case 7: return slab_prec<7>(prec, code);
   }
-  if (prec == 0) return slab_fn<7, double, double>(code);
-  if (prec == 1) return slab_fn<7, float, double>(code);
-  return slab_fn<7, float, float>(code);
+  return nullptr;
 }
 }  // namespace
 

@@ -496,10 +496,10 @@ constexpr int kMaxChunks = 64;
 lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   const int count = (int)b->inst.size();
   // resident groups by (q, precision, variant); the rest streams through HBM
-  std::map<std::tuple<int, int, int>, std::vector<int>> res;   // (q == 7, prec, variant code)
+  std::map<std::tuple<int, int, int>, std::vector<int>> res;   // (q, prec, variant code)
   std::vector<int> str;          // one launch per step (the plain path)
-  std::vector<int> til[2][3];    // temporal blocking, by (q, prec)
-  // slabs, by (q == 7, prec, variant, workgroups per CU)
+  std::vector<int> til[8][3];    // temporal blocking, by (q, prec)
+  // slabs, by (q, prec, variant, workgroups per CU)
   std::map<std::tuple<int, int, int, int>, std::vector<int>> slb;
   // A pass whose resident instances fill less than a quarter of the GPU's LDS
   // leaves most CUs idle; its step time is that of its largest instances, one
@@ -520,13 +520,13 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     if (b->path == 1)
       str.push_back(i);
     else if (b->path == 3)
-      til[h.q == 7][h.prec].push_back(i);
+      til[h.q][h.prec].push_back(i);
     else if (b->path == 4 || !fits)
-      slb[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D, slab_wgs)].push_back(i);
+      slb[std::make_tuple(h.q, h.prec, h.D, slab_wgs)].push_back(i);
     else if (latency && h.n >= kSplitNodes)
-      slb[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D, 8)].push_back(i);
+      slb[std::make_tuple(h.q, h.prec, h.D, 8)].push_back(i);
     else
-      res[std::make_tuple(h.q == 7 ? 1 : 0, h.prec, h.D)].push_back(i);
+      res[std::make_tuple(h.q, h.prec, h.D)].push_back(i);
   }
   // item records of this call go to slot `k`; wait until the copy issued from
   // the same slot two calls ago has been consumed
@@ -544,7 +544,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int pr = std::get<1>(group.first), code = std::get<2>(group.first);
       std::vector<int> g = group.second;
       const size_t es = pr ? sizeof(float) : sizeof(double);
-      const int q = std::get<0>(group.first) ? 7 : 5;
+      const int q = std::get<0>(group.first);
       auto bytes_of = [&](int i) { return ((size_t)q * b->inst[i].n * es + 15) / 16 * 16; };
       // jobs: first-fit decreasing bin packing of equal-step instances into a
       // workgroup's LDS share (half the LDS, or the largest instance)
@@ -669,7 +669,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int qq = std::get<0>(group.first), pr = std::get<1>(group.first), code = std::get<2>(group.first);
       const int wgs = std::get<3>(group.first);
       const std::vector<int>& g = group.second;
-      const int q = qq ? 7 : 5, H = q / 2;
+      const int q = qq, H = q / 2;
       const size_t es = pr ? sizeof(float) : sizeof(double);
       const int W = (int)((b->lim.lds_max / (size_t)wgs - 16) / (q * es));
       int sp = b->tile_steps > 0 ? (b->tile_steps + 1) / 2 * 2 : 16;   // even: strips in natural layout
@@ -769,11 +769,11 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       if (st != LBM_OK) return st;
     }
   }
-  for (int qq = 0; qq < 2; ++qq) {
+  for (int qq = 4; qq < 8; ++qq) {
     for (int pr = 0; pr < 3; ++pr) {
       const std::vector<int>& g = til[qq][pr];
       if (g.empty()) continue;
-      const int q = qq ? 7 : 5, H = q / 2;
+      const int q = qq, H = q / 2;
       const size_t es = pr ? sizeof(float) : sizeof(double);
       const int wgs = b->tile_wgs > 0 ? b->tile_wgs : 2;
       const int W = (int)(b->lim.lds_max / (size_t)wgs / (q * es));
@@ -835,7 +835,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     }
     std::memcpy(b->tiles_host + (size_t)k * b->tiles_cap, tvec.data(), sizeof(DevTile) * tvec.size());
     for (int i : str) (void)i;
-    for (int qq = 0; qq < 2; ++qq)
+    for (int qq = 4; qq < 8; ++qq)
       for (int pr = 0; pr < 3; ++pr) {
         lbm_status st = til[qq][pr].empty() ? LBM_OK : ensure_second_buffer(b, pr != 0);
         if (st != LBM_OK) return st;

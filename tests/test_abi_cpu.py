@@ -52,6 +52,11 @@ def _quartic_family():
                      ((), (0.0, 0.0, 0.5, 0.0, 0.25)) + ((0.0, 1.0),) * 5, 64, 0.1, 1e-4, 1.7)
 
 
+def _random_m5_q6():
+    p = W.random_m6_problem(W.rng(99, 2), 64)
+    return dataclasses.replace(p, alpha=p.alpha[:6] + (0.0,), q=6)
+
+
 PROBLEMS = {
     "kdv": W.kdv(1.0, 64, 0.05, 2e-4, 5.0, 0.0),
     "mkdv": W.mkdv(0.7, 64, 0.1, 1e-4, 2.0, 0.0),
@@ -64,6 +69,12 @@ PROBLEMS = {
     "random_m6_paper_am": dataclasses.replace(W.random_m6_problem(W.rng(99, 1), 64), am=1),
     "quartic_q7": _quartic_family(),
     "ks_on_q7": dataclasses.replace(W.kuramoto_sivashinsky(64, 0.1, 1e-3, 2.0, 0.0), q=7),
+    "kdv_q4": dataclasses.replace(W.kdv(1.0, 64, 0.05, 2e-4, 5.0, 0.0), q=4),
+    "kdv_burgers_q4": W.kdv_burgers(2.0, 0.1, 64, 0.1, 0.01, 1.5, 0.0, q=4),
+    "mkdv_q4": dataclasses.replace(W.mkdv(0.7, 64, 0.1, 1e-4, 2.0, 0.0), q=4),
+    "kawahara_q6": dataclasses.replace(W.kawahara(64, 0.0586, 1.3e-5, 3.0, 0.0), q=6),
+    "dissipative5_q6": W.dissipative_fifth_order(3.0, 1e-3, 0.0625, -1e-3, 64, 0.1, 0.01, 2.0, 0.0, q=6),
+    "random_m5_q6": _random_m5_q6(),
 }
 
 
@@ -89,11 +100,13 @@ def test_validation_rejects_bad_descriptors():
     assert lbm.validate(dataclasses.replace(good, tau=float("nan"))) == lbm.INVALID_ARG
     assert lbm.validate(dataclasses.replace(good, dt=0.0)) == lbm.INVALID_ARG
     assert lbm.validate(dataclasses.replace(good, n=4)) == lbm.INVALID_ARG
-    assert lbm.validate(dataclasses.replace(good, q=6)) == lbm.INVALID_ARG
-    assert lbm.validate(dataclasses.replace(good, q=7)) == lbm.OK
+    for q, want in ((3, lbm.INVALID_ARG), (4, lbm.OK), (5, lbm.OK), (6, lbm.OK), (7, lbm.OK), (8, lbm.INVALID_ARG)):
+        assert lbm.validate(dataclasses.replace(good, q=q)) == want, q
     assert lbm.validate(dataclasses.replace(good, m=2)) == lbm.INVALID_ARG     # alpha_3 != 0 needs m >= 3
     assert lbm.validate(dataclasses.replace(good, scheme=3)) == lbm.INVALID_ARG
     assert lbm.validate(dataclasses.replace(PROBLEMS["kawahara"], q=5)) == lbm.INVALID_ARG
+    assert lbm.validate(dataclasses.replace(PROBLEMS["kawahara"], q=4)) == lbm.INVALID_ARG   # q >= m + 1
+    assert lbm.validate(dataclasses.replace(PROBLEMS["ks"], q=4)) == lbm.INVALID_ARG
     d = lbm.make_desc(good)
     d.pi_deg[1] = 5
     assert lib.lbm_validate(ctypes.byref(d)) == lbm.INVALID_ARG
