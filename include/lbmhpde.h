@@ -10,6 +10,11 @@
  *     f*_j  = f_j - (f_j - f_eq_j) / tau                  (eq. LBE)
  *     f_j(x + e_j dx) = f*_j(x)                           (eq. LBE)
  * on the D1Q5 (e = 0, 1, -1, 2, -2) or D1Q7 (e = 0, +-1, +-2, +-3) lattice,
+ * or on D1Q4 (e = 1, -1, 2, -2) / D1Q6 (e = +-1, +-2, +-3) without a rest
+ * velocity, which Sec. III allows for orders 3 / 5 (M_q^{-1} is then the exact
+ * inverse of the moment matrix M[k][j] = e_j^k; these lattices carry a
+ * checkerboard mode that grows unless a diffusive term is large enough --
+ * lbm_stability reports it),
  * with Pi_bar_0 = phi, Pi_bar_1 = Pi_1/c, Pi_bar_k = (Pi_k0 + beta_k Pi_k)/c^k,
  * c = dx/dt, beta_k = alpha_k / (dt^{k-1} tau_k) (eq. taus and Sec. III.C) and
  * the auxiliary moments Pi_k0 of Sec. II.C-F.
@@ -72,7 +77,7 @@ typedef enum { LBM_AM_CORRECTED = 0, LBM_AM_PAPER = 1 } lbm_am;
 /* Problem descriptor (Sec. II.A eq. NPDE; Sec. III).  Plain data; layout fixed. */
 typedef struct {
   int32_t m;             /* PDE order 1..6; 0 = highest k with alpha[k] != 0 */
-  int32_t q;             /* 5 or 7; 0 = 5 if m <= 4 else 7 (Sec. III); needs q >= m + 1 */
+  int32_t q;             /* 4, 5, 6 or 7; 0 = 5 if m <= 4 else 7 (Sec. III); needs q >= m + 1 */
   int32_t scheme;        /* 1 = all q moments (default, 0 is read as 1); 2 = top moment Pi_bar_{q-1} = 0 */
   int32_t am;            /* lbm_am */
   double alpha[7];       /* alpha[2..6]; alpha[0], alpha[1] ignored (alpha_1 = 1) */
