@@ -290,7 +290,9 @@ KS_DT_CONST = {2.0: 3.125, 10.0: 855.7916666666666, 20.0: 7411.625}
 def serving_request(i: int, n_min: int = 128, n_max: int = 16384, steps_min: int = 1000,
                     steps_max: int = 100000) -> Instance:
     """Request i of the serving mix: a uniformly drawn family, N and steps
-    log-uniform, precision FP32 deviation or FP64 with probability 1/2."""
+    log-uniform, precision FP32 deviation or FP64 with probability 1/2; Kawahara
+    requests use scheme 2 and random sixth-order ones the printed auxiliary
+    moments with probability 1/2."""
     g = rng(5, i)
     fam = SERVING_FAMILIES[int(g.integers(len(SERVING_FAMILIES)))]
     n = int(round(math.exp(g.uniform(math.log(n_min), math.log(n_max)))))
@@ -333,6 +335,10 @@ def serving_request(i: int, n_min: int = 128, n_max: int = 16384, steps_min: int
             p = kawahara(n, dx, min(1.3e-5 * (dx / 0.0586) ** 5, 0.1 * dx), 3.0 if n >= 2048 else 8.0, -60.0,
                          prec=prec)
             phi0 = kawahara_soliton(p.grid(), 0.0, float(g.uniform(-60.0, 60.0)), period=L)
+            # scheme 2 (top moment zero, the variant of Sec. IV's Kawahara-type
+            # examples) for half of the requests
+            if g.random() < 0.5:
+                p = dataclasses.replace(p, scheme=2)
         else:
             # tau = 5: at the batch's tau = 2 the grid-scale mode grows 0.015% per
             # step on fine grids and up to 0.5% on coarse ones (von Neumann), too much
@@ -346,4 +352,7 @@ def serving_request(i: int, n_min: int = 128, n_max: int = 16384, steps_min: int
         p = dataclasses.replace(p, prec=prec, tau=3.0)
         x = p.grid() / (n * p.dx)
         phi0 = 0.3 * np.sin(2 * np.pi * x) + 0.1 * np.cos(6 * np.pi * x + float(g.uniform(0, 6)))
+        # the auxiliary moments as printed (instead of corrected) for half of them
+        if g.random() < 0.5:
+            p = dataclasses.replace(p, am=1)
     return Instance(p, np.ascontiguousarray(phi0, dtype=np.float64), steps)

@@ -86,16 +86,19 @@ def test_results_same_alone_and_in_mix_under_small_budget():
 
 
 def test_served_results_match_oracle():
-    reqs = _requests(14, n_max=600, steps_max=1500, start=100)
+    # requests 100-113 and 142 cover every family, both precisions, scheme 2
+    # (Kawahara) and the printed auxiliary moments (random sixth-order)
+    reqs = _requests(14, n_max=600, steps_max=1500, start=100) + _requests(1, n_max=600, steps_max=1500, start=142)
     srv = lbm.Server(64 << 20, max_slots=64, max_n=2048, block_steps=400)
     out = serving.run_poisson(srv, reqs, rate=1e6, keep_results=True)
     srv.close()
     assert out["nonfinite"] == 0
     checked = set()
     for k, r in enumerate(reqs):
-        if (r.problem.name, r.problem.prec) in checked:
+        key = (r.problem.name, r.problem.prec, r.problem.scheme, r.problem.am)
+        if key in checked:
             continue
-        checked.add((r.problem.name, r.problem.prec))
+        checked.add(key)
         want = O.run(dataclasses.replace(r.problem, prec=W.F64), r.phi0, r.steps)
         tol = 1e-12 if r.problem.prec == W.F64 else (1e-3 if r.problem.name == "ks" else 1e-4)
         err = rel2(out["results"][k], want)
