@@ -16,6 +16,10 @@ What it computes, in the paper's order and notation:
   antiderivatives (zero at phi = 0) of the integrands printed with eqs. (Pi4),
   (Pi5), (Pi6).  All of this is exact rational arithmetic on the binary values
   of the inputs; each coefficient is rounded to FP64 once.
+* Sec. III.C with real n, p, q: Pi_k given with real exponents (problem.gpi)
+  turn every polynomial above into a power sum sum_i c_i phi^{g_i}; the same
+  integrands, exact in Fractions of the binary exponents and coefficients,
+  evaluated as sum_i c_i phi**g_i (phi >= 0).
 * Sec. III.A/B: scaled moments Pi_bar_0 = phi, Pi_bar_1 = Pi_1 / c,
   Pi_bar_k = (Pi_k0 + beta_k Pi_k) / c^k and the equilibrium
   f_eq = M_q^{-1} Pi_bar with the printed integer inverses (1/24, 1/720).
@@ -117,6 +121,67 @@ def pval_exact(p: Poly, x: Fraction) -> Fraction:
     for c in reversed(p):
         acc = acc * x + c
     return acc
+
+
+# Power sums sum_i c_i phi^{g_i} with real exponents g_i >= 0, as
+# {exponent: coefficient} of Fractions: Pi_k with real powers (the families of
+# Sec. III.C with real n, p, q) and everything built from them.
+PSum = Dict[Fraction, Fraction]
+
+
+def _clean(d: PSum) -> PSum:
+    return {e: c for e, c in sorted(d.items()) if c != 0}
+
+
+def sadd(*ps: PSum) -> PSum:
+    out: PSum = {}
+    for p in ps:
+        for e, c in p.items():
+            out[e] = out.get(e, Fraction(0)) + c
+    return _clean(out)
+
+
+def sscale(p: PSum, s) -> PSum:
+    s = Fraction(s)
+    return _clean({e: c * s for e, c in p.items()})
+
+
+def smul(a: PSum, b: PSum) -> PSum:
+    out: PSum = {}
+    for e1, c1 in a.items():
+        for e2, c2 in b.items():
+            out[e1 + e2] = out.get(e1 + e2, Fraction(0)) + c1 * c2
+    return _clean(out)
+
+
+def spow(p: PSum, n: int) -> PSum:
+    out: PSum = {Fraction(0): Fraction(1)}
+    for _ in range(n):
+        out = smul(out, p)
+    return out
+
+
+def sderiv(p: PSum) -> PSum:
+    return _clean({e - 1: c * e for e, c in p.items() if e != 0})
+
+
+def sinteg(p: PSum) -> PSum:
+    """Antiderivative that vanishes at phi = 0 (exponents >= 0)."""
+    return _clean({e + 1: c / (e + 1) for e, c in p.items()})
+
+
+def sconst(c) -> PSum:
+    return _clean({Fraction(0): Fraction(c)})
+
+
+class _Ops:
+    def __init__(self, add, scale, mul, pow_, deriv, integ, const):
+        self.add, self.scale, self.mul, self.pow = add, scale, mul, pow_
+        self.deriv, self.integ, self.const = deriv, integ, const
+
+
+POLY_OPS = _Ops(padd, pscale, pmul, ppow, pderiv, pinteg, pconst)
+SUM_OPS = _Ops(sadd, sscale, smul, spow, sderiv, sinteg, sconst)
 
 
 # ---------------------------------------------------------------------------
@@ -257,6 +322,7 @@ class OracleModel:
         self.Pi_f: Dict[int, np.ndarray] = {}
         self.Pi0_f: Dict[int, np.ndarray] = {}
         self.beta_f: Dict[int, float] = {}
+        self.general = False                # Pi_k are power sums with real exponents
 
 
 class SingularTau(ValueError):
@@ -283,9 +349,27 @@ def build_model(problem) -> OracleModel:
     taus = relaxation_taus(problem.tau)
     mdl.taus = taus
 
-    # Pi_k as given (k = 1..6); absent ones are zero
-    Pi = {k: poly(problem.pi[k]) if k < len(problem.pi) else [] for k in range(1, 7)}
+    # Pi_k as given (k = 1..6); absent ones are zero.  Real powers (problem.gpi)
+    # make every Pi_k a power sum unless all given exponents are integers 0..4.
+    gpi = getattr(problem, "gpi", ())
+    given = {k: tuple(gpi[k]) if k < len(gpi) else () for k in range(1, 7)}
+    general = any(Fraction(e) != int(Fraction(e)) or Fraction(e) > 4
+                  for k in given for e, _ in given[k])
+    Pi = {}
+    for k in range(1, 7):
+        if general:
+            if given[k]:
+                Pi[k] = sadd(*[{Fraction(e): Fraction(c)} for e, c in given[k]])
+            else:
+                coeffs = problem.pi[k] if k < len(problem.pi) else ()
+                Pi[k] = _clean({Fraction(i): Fraction(c) for i, c in enumerate(coeffs)})
+        elif given[k]:
+            Pi[k] = padd(*[[Fraction(0)] * int(Fraction(e)) + [Fraction(c)] for e, c in given[k]])
+        else:
+            Pi[k] = poly(problem.pi[k]) if k < len(problem.pi) else []
     mdl.Pi = Pi
+    mdl.general = general
+    ops = SUM_OPS if general else POLY_OPS
 
     # beta_k = alpha_k / (dt^{k-1} tau_k); zero where alpha_k = 0 (Remarks 2 and 4)
     beta: Dict[int, Fraction] = {}
@@ -322,47 +406,53 @@ def build_model(problem) -> OracleModel:
     mdl.A = {4: A40, 5: A50, 6: A60}
 
     # auxiliary moments: antiderivatives of the integrands of Sec. II
-    d1 = pderiv(Pi[1])
-    dP = {k: pderiv(Pi[k]) for k in range(2, 7)}
+    d1 = ops.deriv(Pi[1])
+    dP = {k: ops.deriv(Pi[k]) for k in range(2, 7)}
     Pi0: Dict[int, Poly] = {}
     # Pi_20 = int (Pi_1')^2
-    Pi0[2] = pinteg(ppow(d1, 2))
+    Pi0[2] = ops.integ(ops.pow(d1, 2))
     # Pi_30 = int [(Pi_1')^3 + 3 beta_2 Pi_2' Pi_1']
-    Pi0[3] = pinteg(padd(ppow(d1, 3), pscale(pmul(dP[2], d1), 3 * b2)))
+    Pi0[3] = ops.integ(ops.add(ops.pow(d1, 3), ops.scale(ops.mul(dP[2], d1), 3 * b2)))
     if q > 4:
         # eq. (Pi4): Pi_40 = int [(Pi_1')^4 + 6 beta_2 Pi_2'(Pi_1')^2 + 4 beta_3 Pi_3' Pi_1' + A_40]
-        Pi0[4] = pinteg(padd(ppow(d1, 4),
-                             pscale(pmul(dP[2], ppow(d1, 2)), 6 * b2),
-                             pscale(pmul(dP[3], d1), 4 * b3),
-                             pconst(A40)))
+        Pi0[4] = ops.integ(ops.add(ops.pow(d1, 4),
+                                   ops.scale(ops.mul(dP[2], ops.pow(d1, 2)), 6 * b2),
+                                   ops.scale(ops.mul(dP[3], d1), 4 * b3),
+                                   ops.const(A40)))
     if q > 5:
         # eq. (Pi5): Pi_50 = int [(Pi_1')^5 + 10 b2 Pi_2'(Pi_1')^3 + 10 b3 Pi_3'(Pi_1')^2 + 5 b4 Pi_4' Pi_1' + A_50]
-        terms = [ppow(d1, 5),
-                 pscale(pmul(dP[2], ppow(d1, 3)), 10 * b2),
-                 pscale(pmul(dP[3], ppow(d1, 2)), 10 * b3),
-                 pscale(pmul(dP[4], d1), 5 * b4),
-                 pconst(A50)]
+        terms = [ops.pow(d1, 5),
+                 ops.scale(ops.mul(dP[2], ops.pow(d1, 3)), 10 * b2),
+                 ops.scale(ops.mul(dP[3], ops.pow(d1, 2)), 10 * b3),
+                 ops.scale(ops.mul(dP[4], d1), 5 * b4),
+                 ops.const(A50)]
         if corrected:
-            terms.append(pscale(d1, 5 * A40))
-        Pi0[5] = pinteg(padd(*terms))
+            terms.append(ops.scale(d1, 5 * A40))
+        Pi0[5] = ops.integ(ops.add(*terms))
     if q > 6:
         # eq. (Pi6): Pi_60 = int [(Pi_1')^6 + 15 b2 Pi_2'(Pi_1')^4 + 20 b3 Pi_3'(Pi_1')^3
         #                        + 15 b4 Pi_4'(Pi_1')^2 + 6 b5 Pi_5' Pi_1' + A_60]
-        terms = [ppow(d1, 6),
-                 pscale(pmul(dP[2], ppow(d1, 4)), 15 * b2),
-                 pscale(pmul(dP[3], ppow(d1, 3)), 20 * b3),
-                 pscale(pmul(dP[4], ppow(d1, 2)), 15 * b4),
-                 pscale(pmul(dP[5], d1), 6 * b5),
-                 pconst(A60)]
+        terms = [ops.pow(d1, 6),
+                 ops.scale(ops.mul(dP[2], ops.pow(d1, 4)), 15 * b2),
+                 ops.scale(ops.mul(dP[3], ops.pow(d1, 3)), 20 * b3),
+                 ops.scale(ops.mul(dP[4], ops.pow(d1, 2)), 15 * b4),
+                 ops.scale(ops.mul(dP[5], d1), 6 * b5),
+                 ops.const(A60)]
         if corrected:
-            terms.append(pscale(ppow(d1, 2), 15 * A40))
-            terms.append(pscale(d1, 6 * A50))
-        Pi0[6] = pinteg(padd(*terms))
+            terms.append(ops.scale(ops.pow(d1, 2), 15 * A40))
+            terms.append(ops.scale(d1, 6 * A50))
+        Pi0[6] = ops.integ(ops.add(*terms))
     mdl.Pi0 = Pi0
 
     # FP64 roundings (each exact value rounded once)
-    mdl.Pi_f = {k: np.array([float(c) for c in Pi[k]] or [0.0]) for k in range(1, 7)}
-    mdl.Pi0_f = {k: np.array([float(c) for c in p] or [0.0]) for k, p in Pi0.items()}
+    if general:   # (exponents, coefficients)
+        mdl.Pi_f = {k: (np.array([float(e) for e in Pi[k]]), np.array([float(c) for c in Pi[k].values()]))
+                    for k in range(1, 7)}
+        mdl.Pi0_f = {k: (np.array([float(e) for e in p]), np.array([float(c) for c in p.values()]))
+                     for k, p in Pi0.items()}
+    else:
+        mdl.Pi_f = {k: np.array([float(c) for c in Pi[k]] or [0.0]) for k in range(1, 7)}
+        mdl.Pi0_f = {k: np.array([float(c) for c in p] or [0.0]) for k, p in Pi0.items()}
     mdl.beta_f = {k: float(b) for k, b in beta.items()}
     mdl.minv, mdl.minv_den = inverse_moment_matrix(q)
     return mdl
@@ -376,15 +466,27 @@ def _polyval(coeffs: np.ndarray, x: np.ndarray) -> np.ndarray:
     return np.polynomial.polynomial.polyval(x, coeffs)
 
 
+def _sumval(terms, x: np.ndarray) -> np.ndarray:
+    """sum_i c_i x^{g_i} for (exponents, coefficients); x >= 0 where g_i is not an integer."""
+    exps, coefs = terms
+    out = np.zeros_like(x)
+    for e, c in zip(exps, coefs):
+        out = out + c * (np.ones_like(x) if e == 0 else x ** e)
+    return out
+
+
 def scaled_moments(mdl: OracleModel, phi: np.ndarray) -> np.ndarray:
     """Pi_bar_k(phi), k = 0..q-1 (Sec. III.A/B); shape (q, N)."""
-    phi = np.asarray(phi, dtype=np.float64)
+    phi = np.asarray(phi)
+    if not np.iscomplexobj(phi):
+        phi = phi.astype(np.float64)
+    ev = _sumval if getattr(mdl, "general", False) else _polyval
     c = mdl.c
-    pbar = np.empty((mdl.q,) + phi.shape)
+    pbar = np.empty((mdl.q,) + phi.shape, dtype=phi.dtype)
     pbar[0] = phi
-    pbar[1] = _polyval(mdl.Pi_f[1], phi) / c
+    pbar[1] = ev(mdl.Pi_f[1], phi) / c
     for k in range(2, mdl.q):
-        pbar[k] = (_polyval(mdl.Pi0_f[k], phi) + mdl.beta_f[k] * _polyval(mdl.Pi_f[k], phi)) / c ** k
+        pbar[k] = (ev(mdl.Pi0_f[k], phi) + mdl.beta_f[k] * ev(mdl.Pi_f[k], phi)) / c ** k
     if mdl.scheme == 2:
         pbar[mdl.q - 1] = 0.0
     return pbar

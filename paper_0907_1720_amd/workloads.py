@@ -48,13 +48,19 @@ class Problem:
     x0: float = 0.0                     # x_i = x0 + i*dx
     name: str = ""
     bc: int = 0                         # 0 periodic; 1 / 2 bounded: equilibrium / NEE layers
+    # non-polynomial Pi_k: gpi[k] = ((exponent, coefficient), ...) replaces pi[k]
+    # when non-empty (real powers of phi, Sec. III.C)
+    gpi: Tuple[Tuple[Tuple[float, float], ...], ...] = ()
+
+    def has_pi(self, k: int) -> bool:
+        return (k < len(self.gpi) and len(self.gpi[k]) > 0) or len(self.pi[k]) > 0
 
     def order(self) -> int:
         if self.m:
             return self.m
         m = 1
         for k in range(2, 7):
-            if self.alpha[k] != 0.0 and len(self.pi[k]) > 0:
+            if self.alpha[k] != 0.0 and self.has_pi(k):
                 m = k
         return m
 
@@ -122,6 +128,32 @@ def dissipative_fifth_order(nu, delta, mu, eps, n, dx, dt, tau, x0, **kw) -> Pro
     return Problem(_alpha(a2=-nu, a3=delta, a4=mu, a5=eps),
                    _pis(p1=(0, 0, 0.5), p2=(0, 1), p3=(0, 1), p4=(0, 1), p5=(0, 1)),
                    n, dx, dt, tau, x0=x0, name="dissipative5", **kw)
+
+
+def power_kdv(power, delta, n, dx, dt, tau, x0, nu=0.0, **kw) -> Problem:
+    """phi_t + phi^power phi_x - nu phi_xx + delta phi_xxx = 0 with a real power
+    >= 0 (Sec. III.C family with beta u^n u_x): Pi_1 = phi^(power+1)/(power+1);
+    needs phi >= 0."""
+    return Problem(_alpha(a2=-nu, a3=delta), _pis(p2=(0, 1) if nu else (), p3=(0, 1)), n, dx, dt, tau,
+                   x0=x0, name="power_kdv",
+                   gpi=((), ((power + 1.0, 1.0 / (power + 1.0)),), (), (), (), (), ()), **kw)
+
+
+def family_b(a, b, npow, a2, p, a3, qpow, n, dx, dt, tau, x0, **kw) -> Problem:
+    """phi_t + a phi phi_x + b phi^npow phi_x + a2 (phi^p)_xx + a3 (phi^qpow)_xxx = 0
+    (the third-order family of Sec. III.C with real n, p, q; p, q >= 1)."""
+    return Problem(_alpha(a2=a2, a3=a3), _pis(), n, dx, dt, tau, x0=x0, name="family_b",
+                   gpi=((), ((2.0, a / 2.0), (npow + 1.0, b / (npow + 1.0))), ((p, 1.0),), ((qpow, 1.0),),
+                        (), (), ()), **kw)
+
+
+def family_a(a, b, npow, alphas, n, dx, dt, tau, x0, **kw) -> Problem:
+    """phi_t + a phi phi_x + b phi^npow phi_x + sum_k alpha_k d^k phi = 0, k = 2..6
+    (the sixth-order family of Sec. III.C with a real n)."""
+    al = dict(zip(("a2", "a3", "a4", "a5", "a6"), alphas))
+    return Problem(_alpha(**al), _pis(p2=(0, 1), p3=(0, 1), p4=(0, 1), p5=(0, 1), p6=(0, 1)), n, dx, dt, tau,
+                   x0=x0, name="family_a",
+                   gpi=((), ((2.0, a / 2.0), (npow + 1.0, b / (npow + 1.0))), (), (), (), (), ()), **kw)
 
 
 def k22(n, dx, dt, tau, x0, **kw) -> Problem:

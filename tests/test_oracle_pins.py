@@ -604,3 +604,171 @@ def test_second_order_convergence_kdv():
         errs.append(rel2(phi, W.kdv_soliton(x, steps * dt, 1.0, 1.0, -5.0, period=L)))
     order = math.log2(errs[1] / errs[2])
     assert order >= 1.8, errs
+
+
+# ---------------------------------------------------------------------------
+# Sec. III.C with real powers: beta u^n u_x, alpha_2 (u^p)_xx, alpha_3 (u^q)_xxx
+# ---------------------------------------------------------------------------
+
+def _sum_int_pi1_pow(k, a, b, n):
+    """eq. (intPi1k) for Pi_1' = a u + b u^n with real n: u sum_j C(k,j)/(jn+k+1-j) (a u)^{k-j} (b u^n)^j."""
+    out = {}
+    for j in range(k + 1):
+        e = (k - j) + j * n + 1
+        c = Fraction(math.comb(k, j)) / (j * n + k + 1 - j) * a ** (k - j) * b ** j
+        out = O.sadd(out, {e: c})
+    return out
+
+
+def _u(e=1):
+    return {Fraction(e): Fraction(1)}
+
+
+@pytest.mark.parametrize("npow", [0.5, 1.5, 0.25, 2.75])
+def test_aux_moments_match_family_a_closed_forms_real_n(npow):
+    a_, b_ = 0.75, -0.625
+    alpha = (0.25, -0.5, 0.125, -0.375, 0.0625)
+    p = W.family_a(a_, b_, npow, alpha, 16, 0.125, 0.0078125, 1.75, 0.0, q=7, am=1)
+    mdl = O.build_model(p)
+    assert mdl.general
+    n = Fraction(npow)
+    A = Fraction(a_)
+    B = Fraction(b_ / (npow + 1.0)) * (n + 1)   # the coefficient of u^{n+1} is B/(n+1)
+    b = mdl.beta
+    Pi1 = O.sadd({Fraction(2): A / 2}, {n + 1: B / (n + 1)})
+    I = {k: _sum_int_pi1_pow(k, A, B, n) for k in range(2, 7)}
+    u = _u()
+    want = {   # eq. (Pi30t60) as printed, Pi_k = u for k >= 2
+        2: I[2],
+        3: O.sadd(I[3], O.sscale(Pi1, 3 * b[2])),
+        4: O.sadd(I[4], O.sscale(I[2], 6 * b[2]), O.sscale(Pi1, 4 * b[3]), O.sscale(u, mdl.A[4])),
+        5: O.sadd(I[5], O.sscale(I[3], 10 * b[2]), O.sscale(I[2], 10 * b[3]), O.sscale(Pi1, 5 * b[4]),
+                  O.sscale(u, mdl.A[5])),
+        6: O.sadd(I[6], O.sscale(I[4], 15 * b[2]), O.sscale(I[3], 20 * b[3]), O.sscale(I[2], 15 * b[4]),
+                  O.sscale(Pi1, 6 * b[5]), O.sscale(u, mdl.A[6])),
+    }
+    for k in range(2, 7):
+        assert mdl.Pi0[k] == want[k], k
+
+
+@pytest.mark.parametrize("npow,pp,qq", [(0.5, 1.5, 2.5), (1.25, 1.0, 1.75), (2.5, 2.25, 1.0)])
+def test_aux_moments_match_family_b_closed_forms_real_powers(npow, pp, qq):
+    """eq. (3Pi20t40) with real n, p, q."""
+    a_, b_ = 0.5, 0.75
+    p = W.family_b(a_, b_, npow, -0.25, pp, 0.5, qq, 16, 0.25, 0.015625, 1.25, 0.0, q=5, am=1)
+    mdl = O.build_model(p)
+    assert mdl.general
+    n, P_, Q_ = Fraction(npow), Fraction(pp), Fraction(qq)
+    A = Fraction(a_)
+    B = Fraction(b_ / (npow + 1.0)) * (n + 1)
+    b = mdl.beta
+
+    def mono(e, c):
+        return {Fraction(e): Fraction(c)}
+
+    Pi30 = O.sadd(_sum_int_pi1_pow(3, A, B, n),
+                  O.sscale(O.sadd(mono(P_ + 1, A / (P_ + 1)), mono(P_ + n, B / (P_ + n))), 3 * b[2] * P_))
+    Pi40 = O.sadd(_sum_int_pi1_pow(4, A, B, n),
+                  O.sscale(O.sadd(mono(P_ + 2, A ** 2 / (P_ + 2)), mono(P_ + n + 1, 2 * A * B / (P_ + n + 1)),
+                                  mono(P_ + 2 * n, B ** 2 / (P_ + 2 * n))), 6 * b[2] * P_),
+                  O.sscale(O.sadd(mono(Q_ + 1, A / (Q_ + 1)), mono(Q_ + n, B / (Q_ + n))), 4 * b[3] * Q_),
+                  mono(1, mdl.A[4]))
+    assert mdl.Pi0[2] == _sum_int_pi1_pow(2, A, B, n)
+    assert mdl.Pi0[3] == Pi30
+    assert mdl.Pi0[4] == Pi40
+
+
+def test_integer_real_powers_equal_polynomials():
+    """Given as real powers, integer exponents <= 4 give the polynomial model itself."""
+    p = W.family_b(0.5, 0.75, 2.0, -0.25, 1.0, 0.5, 2.0, 16, 0.25, 0.015625, 1.25, 0.0, q=5)
+    poly = W.Problem(p.alpha, W._pis(p1=(0, 0, 0.25, 0.25), p2=(0, 1), p3=(0, 0, 1)), 16, 0.25, 0.015625, 1.25, q=5)
+    a, b = O.build_model(p), O.build_model(poly)
+    assert not a.general
+    for k in range(2, 5):
+        assert a.Pi0[k] == b.Pi0[k]
+
+
+def _power_problems():
+    return [
+        W.power_kdv(1.5, 0.01, 64, 0.1, 1e-3, 2.0, 0.0, nu=0.05),
+        # D1Q4 / D1Q6 need strong diffusion (the checkerboard mode, see above)
+        W.power_kdv(0.5, 0.02, 64, 0.1, 0.01, 2.0, 0.0, nu=3.0, q=4),
+        W.family_b(0.5, 0.75, 0.5, -0.05, 1.5, 0.01, 2.5, 64, 0.1, 1e-3, 2.0, 0.0),
+        W.family_a(0.5, 0.5, 1.5, (-0.05, 0.01, 1e-4, 0.0, 0.0), 64, 0.1, 1e-3, 2.0, 0.0, q=7),
+        W.family_a(0.0, 1.0, 1.0 / 3.0, (-3.0, 1e-3, 0.0625, -1e-3, 0.0), 64, 0.1, 0.01, 2.0, 0.0, q=6),
+    ]
+
+
+@pytest.mark.parametrize("idx", range(5))
+def test_real_power_moment_identities(idx):
+    p = _power_problems()[idx]
+    mdl = O.build_model(p)
+    assert mdl.general
+    phi = np.random.default_rng(idx).uniform(0.05, 2.5, 257)
+    feq = O.equilibrium(mdl, phi)
+    pbar = O.scaled_moments(mdl, phi)
+    e = mdl.e.astype(np.float64)
+    for k in range(mdl.q):
+        mom = (e[:, None] ** k * feq).sum(axis=0)
+        scale = np.abs(e[:, None] ** k * feq).sum(axis=0) + 1e-300
+        assert np.max(np.abs(mom - pbar[k]) / scale) < 1e-14, k
+    # the first moment is the given flux, evaluated directly
+    pi1 = sum(c * phi ** ex for ex, c in p.gpi[1])
+    flux = (e[:, None] * feq).sum(axis=0) * mdl.c
+    terms = np.abs(e[:, None] * feq).sum(axis=0) * mdl.c + np.abs(pi1)
+    assert np.max(np.abs(flux - pi1) / terms) < 1e-14
+
+
+@pytest.mark.parametrize("idx", range(5))
+def test_real_power_sum_phi_conserved(idx):
+    p = dataclasses.replace(_power_problems()[idx], n=96)
+    mdl = O.build_model(p)
+    x = np.arange(p.n)
+    phi0 = 1.0 + 0.4 * np.exp(-((x - 40.0) / 6.0) ** 2)
+    phi = O.run(p, phi0, 300, mdl=mdl)
+    assert np.all(np.isfinite(phi)) and phi.min() > 0
+    assert abs(phi.sum() - phi0.sum()) <= 1e-13 * np.abs(phi0).sum()
+
+
+@pytest.mark.parametrize("m,q,npow", [(3, 5, 1.5), (3, 4, 0.5), (5, 7, 0.25), (5, 6, 2.5), (6, 7, 1.5)])
+def test_real_power_linear_dispersion(m, q, npow):
+    """Linearised about phi_bar > 0, phi_t + phi^n phi_x + sum alpha_k d^k phi = 0
+    is advection at speed a = phi_bar^n plus the linear terms; the scheme's
+    physical eigenvalue must match it to O(kappa^q).  f_eq'(phi_bar) from the
+    oracle's exact power sums, evaluated at 60 digits."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 60
+    tau, pb = 1.3, mp.mpf(7) / 10
+    alphas = tuple(ALPHA[k] if k <= m else 0.0 for k in range(2, 7))
+    p = W.family_a(0.0, 1.0, npow, alphas, 16, 1.0, 1.0, tau, 0.0, q=q, m=m)
+    mdl = O.build_model(p)
+    assert mdl.general
+
+    def dval(ps):   # d/dphi sum c phi^g at phi_bar
+        return sum(mp.mpf(c.numerator) / c.denominator * mp.mpf(g.numerator) / g.denominator
+                   * pb ** (mp.mpf(g.numerator) / g.denominator - 1) for g, c in ps.items() if g != 0)
+
+    s = [mp.mpf(1), dval(mdl.Pi[1])]
+    for k in range(2, q):
+        s.append(dval(mdl.Pi0[k]) + mp.mpf(mdl.beta[k].numerator) / mdl.beta[k].denominator * dval(mdl.Pi[k]))
+    Minv = O.inverse_moment_matrix_exact(q)
+    w = [sum(mp.mpf(Minv[j][k].numerator) / Minv[j][k].denominator * s[k] for k in range(q)) for j in range(q)]
+    # a = Pi_1'(phi_bar) of the flux as given (its coefficient 1/(n+1) is
+    # rounded to binary), within 1e-16 of phi_bar^n
+    a = dval(mdl.Pi[1])
+    assert abs(a / pb ** (mp.mpf(Fraction(npow).numerator) / Fraction(npow).denominator) - 1) < 1e-15
+    om = mp.mpf(1) / mp.mpf(tau)
+    al = [0.0, 1.0] + list(alphas)
+    errs = []
+    for kap in (0.0005, 0.001, 0.002, 0.004):
+        kap = mp.mpf(kap)
+        Amat = mp.matrix(q, q)
+        for j in range(q):
+            ph = mp.exp(-1j * kap * O.lattice_velocities(q)[j])
+            for l in range(q):
+                Amat[j, l] = ph * (om * w[j] + ((1 - om) if j == l else 0))
+        lam = min(mp.eig(Amat, left=False, right=False), key=lambda z: abs(z - 1))
+        target = -(1j * a * kap + sum(al[k] * (1j * kap) ** k for k in range(2, m + 1)))
+        errs.append(abs(mp.log(lam) - target))
+    slopes = [float(mp.log(errs[i + 1] / errs[i]) / mp.log(2)) for i in range(len(errs) - 1)]
+    assert min(slopes) > q - 0.1, slopes
