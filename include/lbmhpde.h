@@ -88,6 +88,21 @@ typedef struct {
   double dx, dt, tau;    /* lattice speed c = dx/dt (Sec. II.A); tau > 1/2 */
   int32_t bc;            /* lbm_bc */
   int32_t prec;          /* lbm_precision */
+  /* Non-polynomial Pi_k (Sec. III.C: the families with real powers beta u^n u_x,
+     alpha_2 (u^p)_xx, alpha_3 (u^q)_xxx): for k = 1..6 with pi_terms[k] > 0,
+       Pi_k(phi) = sum_{i < pi_terms[k]} pi_gcoef[k][i] phi^pi_gexp[k][i]
+     replaces pi_deg / pi_coef[k].  At most 4 terms; every exponent is 0 or in
+     [1, 8].  A model whose equilibrium has non-integer powers of phi needs
+     phi >= 0 (lbm_load_phi rejects a negative phi0; a state that turns
+     negative becomes non-finite and is reported as LBM_ERR_NONFINITE); its
+     equilibrium may use at most 4 distinct fractional parts of the exponents
+     and integer degree 11 within each (LBM_ERR_UNSUPPORTED otherwise), and
+     LBM_F32_DEV_ARITH32 is not available for it.  pi_terms[k] = 0 (a zeroed
+     tail): the polynomial fields apply. */
+  int32_t pi_terms[7];
+  int32_t pi_pad_;
+  double pi_gexp[7][4];
+  double pi_gcoef[7][4];
 } lbm_desc;
 
 typedef struct lbm_problem_s* lbm_problem;
@@ -110,6 +125,15 @@ lbm_status lbm_validate(const lbm_desc* d);
    capacity of G in doubles; *q_out, *degree_out receive q and D. */
 lbm_status lbm_coefficients(const lbm_desc* d, double* G, int32_t cap, int32_t* q_out,
                             int32_t* degree_out);
+/* Models with non-integer powers of phi (pi_terms) make lbm_coefficients
+   return LBM_ERR_UNSUPPORTED; this host-only call covers every model:
+     f_eq_j(phi) = sum_{c < F} phi^nu[c] sum_d G[(c*q + j)*(D+1) + d] phi^d,
+   nu[0] = 0 and nu[c] in (0, 1) the distinct fractional parts of the
+   exponents (a polynomial model has F = 1).  nu holds at least 4 doubles;
+   `cap` is the capacity of G in doubles; *classes_out, *q_out, *degree_out
+   receive F, q and D. */
+lbm_status lbm_coefficients_general(const lbm_desc* d, double* nu, double* G, int32_t cap, int32_t* classes_out,
+                                    int32_t* q_out, int32_t* degree_out);
 
 /* Host-only linear (von Neumann) pre-check: the largest growth factor per step
    over Fourier modes kappa in (0, pi] of the scheme linearised about uniform
@@ -117,7 +141,8 @@ lbm_status lbm_coefficients(const lbm_desc* d, double* G, int32_t cap, int32_t* 
    E(kappa)((1 - 1/tau) I + (1/tau) f_eq'(phi) 1^T)), and its steps-th power.
    Physical growth (e.g. the unstable band of Kuramoto-Sivashinsky) is
    included; a value far above 1 on the grid scale marks parameters (dx, dt,
-   tau) on which the scheme itself amplifies. */
+   tau) on which the scheme itself amplifies.  For a model with non-integer
+   powers of phi, phi_min must be > 0 (LBM_ERR_INVALID_ARG otherwise). */
 lbm_status lbm_stability(const lbm_desc* d, double phi_min, double phi_max, int64_t steps,
                          double* growth_per_step, double* amplification);
 

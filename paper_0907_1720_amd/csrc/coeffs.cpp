@@ -13,6 +13,7 @@
 //    (Vandermonde) matrix M[k][j] = e_j^k of Sec. III.A/B.
 #include "coeffs.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -73,6 +74,87 @@ QPoly antideriv(const QPoly& a) {   // vanishes at phi = 0
   QPoly r(a.size() + 1, 0);
   for (size_t i = 0; i < a.size(); ++i) r[i + 1] = a[i] / (qf)(i + 1);
   return trim(r);
+}
+
+QPoly constant(const QPoly*, qf v) { return trim(QPoly{v}); }
+QPoly identity(const QPoly*) { return QPoly{0, 1}; }
+
+// Power sums with real exponents, sum_i c_i phi^{g_i} (exponents >= 0): the
+// closure of the operations the auxiliary moments need when Pi_k carries real
+// powers (Sec. III.C).  Terms sorted by exponent, no zero coefficients.
+struct GPoly {
+  std::vector<std::pair<qf, qf>> t;   // (exponent, coefficient)
+};
+
+GPoly normal(std::vector<std::pair<qf, qf>> v) {
+  std::sort(v.begin(), v.end(),
+            [](const std::pair<qf, qf>& a, const std::pair<qf, qf>& b) { return a.first < b.first; });
+  GPoly r;
+  for (const auto& e : v) {
+    if (!r.t.empty() && r.t.back().first == e.first)
+      r.t.back().second += e.second;
+    else
+      r.t.push_back(e);
+  }
+  GPoly o;
+  for (const auto& e : r.t)
+    if (e.second != 0) o.t.push_back(e);
+  return o;
+}
+
+GPoly add(const GPoly& a, const GPoly& b) {
+  std::vector<std::pair<qf, qf>> v = a.t;
+  v.insert(v.end(), b.t.begin(), b.t.end());
+  return normal(v);
+}
+
+GPoly scale(const GPoly& a, qf s) {
+  std::vector<std::pair<qf, qf>> v;
+  for (const auto& e : a.t) v.push_back({e.first, e.second * s});
+  return normal(v);
+}
+
+GPoly mul(const GPoly& a, const GPoly& b) {
+  std::vector<std::pair<qf, qf>> v;
+  for (const auto& x : a.t)
+    for (const auto& y : b.t) v.push_back({x.first + y.first, x.second * y.second});
+  return normal(v);
+}
+
+GPoly power(const GPoly& a, int n) {
+  GPoly r;
+  r.t.push_back({0, 1});
+  for (int i = 0; i < n; ++i) r = mul(r, a);
+  return r;
+}
+
+GPoly deriv(const GPoly& a) {
+  std::vector<std::pair<qf, qf>> v;
+  for (const auto& e : a.t)
+    if (e.first != 0) v.push_back({e.first - 1, e.second * e.first});
+  return normal(v);
+}
+
+GPoly antideriv(const GPoly& a) {   // vanishes at phi = 0 (exponents >= 0)
+  std::vector<std::pair<qf, qf>> v;
+  for (const auto& e : a.t) v.push_back({e.first + 1, e.second / (e.first + 1)});
+  return normal(v);
+}
+
+GPoly constant(const GPoly*, qf v) {
+  GPoly r;
+  if (v != 0) r.t.push_back({0, v});
+  return r;
+}
+GPoly identity(const GPoly*) {
+  GPoly r;
+  r.t.push_back({1, 1});
+  return r;
+}
+
+qf floorq(qf x) {   // exponents here are small and non-negative
+  qf f = (qf)(long long)x;
+  return f > x ? f - 1 : f;
 }
 
 qf qabs(qf x) { return x < 0 ? -x : x; }
@@ -146,12 +228,129 @@ bool invert_moment_matrix(int q, qf inv[kMaxQ][kMaxQ]) {
 
 constexpr double kSingular = 1e-10;   // |tau_k| below this is treated as a root
 
+// Pi_k0 = int_0^phi I_k, k = 2..q-1, with the integrand pattern of eqs. (Pi4),
+// (Pi5), (Pi6), and the scaled moments Pi_bar_k (Sec. III.A/B), for
+// polynomials (QPoly) and real-exponent power sums (GPoly) alike
+template <class P>
+void scaled_moments(const P Pi[7], const qf beta[7], const qf A[7], bool corrected, int q, qf c, int scheme,
+                    P Pbar[kMaxQ]) {
+  const P* tag = nullptr;
+  const P d1 = deriv(Pi[1]);
+  P d1pow[7];
+  for (int p = 0; p <= 6; ++p) d1pow[p] = power(d1, p);
+  P Pi0[7];
+  for (int k = 2; k < q; ++k) {
+    P I = d1pow[k];
+    for (int r = 2; r <= k - 1; ++r) {
+      P lead = scale(deriv(Pi[r]), beta[r]);
+      if (corrected && (r == 4 || r == 5)) lead = add(lead, constant(tag, A[r]));
+      I = add(I, scale(mul(lead, d1pow[k - r]), (qf)binom(k, r)));
+    }
+    if (k >= 4) I = add(I, constant(tag, A[k]));
+    Pi0[k] = antideriv(I);
+  }
+  Pbar[0] = identity(tag);
+  Pbar[1] = scale(Pi[1], 1 / c);
+  qf ck = c;
+  for (int k = 2; k < q; ++k) {
+    ck *= c;
+    Pbar[k] = scale(add(Pi0[k], scale(Pi[k], beta[k])), 1 / ck);
+  }
+  if (scheme == 2) Pbar[q - 1] = P();
+}
+
+// Exponents closer than this are evaluated with one fractional part: sums of
+// binary inputs that stand for the same fraction (3 * 1/3 next to 1, 4/3 next
+// to 1 + 1/3) differ by a few units in the last place; the power then changes
+// by at most kGTol * |ln phi| relative.
+constexpr double kGTol = 1e-13;
+
+// class (fractional part) and integer degree of exponent g: g ~ nu[c] + d
+void split_exponent(qf g, std::vector<qf>* nus, int* cls, int* deg) {
+  qf r = floorq(g + (qf)0.5);
+  if (qabs(g - r) <= kGTol) {
+    *cls = 0;
+    *deg = (int)r;
+    return;
+  }
+  const qf fl = floorq(g), fr = g - fl;
+  *deg = (int)fl;
+  for (size_t c = 1; c < nus->size(); ++c)
+    if (qabs((*nus)[c] - fr) <= kGTol) {
+      *cls = (int)c;
+      return;
+    }
+  nus->push_back(fr);
+  *cls = (int)nus->size() - 1;
+}
+
+// f_eq_j = sum_k M^{-1}[j][k] Pi_bar_k as power sums, sorted into classes by
+// the fractional part of the exponent: phi^g = phi^nu phi^d, nu = g - floor(g)
+lbm_status collapse_general(const GPoly Pbar[kMaxQ], const qf inv[kMaxQ][kMaxQ], int q, qf omega, Model* mdl) {
+  GPoly G[kMaxQ];
+  std::vector<qf> nus{0};
+  for (int j = 0; j < q; ++j) {
+    for (int k = 0; k < q; ++k) G[j] = add(G[j], scale(Pbar[k], inv[j][k]));
+    for (const auto& e : G[j].t) {
+      int c, dg;
+      split_exponent(e.first, &nus, &c, &dg);
+      if (dg > kGDeg) return LBM_ERR_UNSUPPORTED;
+    }
+  }
+  if ((int)nus.size() > kGClasses) return LBM_ERR_UNSUPPORTED;
+  std::sort(nus.begin() + 1, nus.end());
+  mdl->gF = (int)nus.size();
+  int D = 1;
+  for (int c = 0; c < mdl->gF; ++c) {
+    mdl->gnuq[c] = nus[c];
+    mdl->gnu[c] = (double)nus[c];
+  }
+  for (int j = 0; j < q; ++j) {
+    for (const auto& e : G[j].t) {
+      int c, dg;
+      split_exponent(e.first, &nus, &c, &dg);
+      mdl->gGq[c][j][dg] += e.second;
+      D = std::max(D, dg);
+    }
+  }
+  mdl->D = D;
+  for (int c = 0; c < mdl->gF; ++c)
+    for (int j = 0; j < q; ++j)
+      for (int dg = 0; dg <= kGDeg; ++dg) {
+        mdl->gG[c][j][dg] = (double)mdl->gGq[c][j][dg];
+        mdl->gwG[c][j][dg] = (double)(omega * mdl->gGq[c][j][dg]);
+        if (!finite_d(mdl->gG[c][j][dg]) || !finite_d(mdl->gwG[c][j][dg])) return LBM_ERR_SINGULAR_TAU;
+      }
+  return LBM_OK;
+}
+
 }  // namespace
+
+long double general_feq(const Model& m, int j, long double phi) {
+  long double acc = 0;
+  for (int c = 0; c < m.gF; ++c) {
+    long double p = 0;
+    for (int dg = kGDeg; dg >= 0; --dg) p = p * phi + (long double)m.gGq[c][j][dg];
+    acc += (c == 0 ? 1.0L : powl(phi, (long double)m.gnuq[c])) * p;
+  }
+  return acc;
+}
+
+long double general_dfeq(const Model& m, int j, long double phi) {
+  long double acc = 0;
+  for (int c = 0; c < m.gF; ++c)
+    for (int dg = 0; dg <= kGDeg; ++dg) {
+      const long double g = (long double)m.gnuq[c] + dg;
+      const long double v = (long double)m.gGq[c][j][dg];
+      if (v != 0 && g != 0) acc += v * g * powl(phi, g - 1);
+    }
+  return acc;
+}
 
 int resolved_order(const lbm_desc& d) {
   int top = 1;
   for (int k = 2; k <= 6; ++k)
-    if (d.alpha[k] != 0.0 && d.pi_deg[k] >= 0) top = k;
+    if (d.alpha[k] != 0.0 && (d.pi_deg[k] >= 0 || d.pi_terms[k] > 0)) top = k;
   if (d.m == 0) return top;
   if (d.m < 1 || d.m > 6 || d.m < top) return 0;
   return d.m;
@@ -177,6 +376,12 @@ lbm_status build_model(const lbm_desc& d, Model* out) {
     if (d.pi_deg[k] < -1 || d.pi_deg[k] > 4) return LBM_ERR_INVALID_ARG;
     for (int p = 0; p <= d.pi_deg[k]; ++p)
       if (!finite_d(d.pi_coef[k][p])) return LBM_ERR_INVALID_ARG;
+    if (d.pi_terms[k] < 0 || d.pi_terms[k] > 4) return LBM_ERR_INVALID_ARG;
+    for (int i = 0; i < d.pi_terms[k]; ++i) {
+      const double e = d.pi_gexp[k][i];
+      if (!finite_d(e) || !finite_d(d.pi_gcoef[k][i]) || !(e == 0.0 || (e >= 1.0 && e <= 8.0)))
+        return LBM_ERR_INVALID_ARG;
+    }
     if (!finite_d(d.alpha[k])) return LBM_ERR_INVALID_ARG;
   }
   if (!(d.dx > 0) || !(d.dt > 0) || !finite_d(d.dx) || !finite_d(d.dt)) return LBM_ERR_INVALID_ARG;
@@ -199,18 +404,38 @@ lbm_status build_model(const lbm_desc& d, Model* out) {
   qf tk[7];
   relaxation_series(tau, tk);
 
-  // ---- Pi_k as polynomials ----
+  // ---- Pi_k: polynomials, or power sums when a given exponent is not an
+  // integer in 0..4 ----
   QPoly Pi[7];
+  GPoly gPi[7];
+  bool general = false;
   for (int k = 1; k <= 6; ++k) {
+    std::vector<std::pair<qf, qf>> v;
+    if (d.pi_terms[k] > 0) {
+      for (int i = 0; i < d.pi_terms[k]; ++i) {
+        const qf e = d.pi_gexp[k][i];
+        if (e != floorq(e) || e > 4) general = true;
+        v.push_back({e, (qf)d.pi_gcoef[k][i]});
+      }
+    } else {
+      for (int i = 0; i <= d.pi_deg[k]; ++i) v.push_back({(qf)i, (qf)d.pi_coef[k][i]});
+    }
+    gPi[k] = normal(v);
+  }
+  for (int k = 1; k <= 6 && !general; ++k) {
     QPoly p;
-    for (int i = 0; i <= d.pi_deg[k]; ++i) p.push_back((qf)d.pi_coef[k][i]);
+    for (const auto& e : gPi[k].t) {
+      const int i = (int)e.first;
+      if ((int)p.size() <= i) p.resize(i + 1, 0);
+      p[i] += e.second;
+    }
     Pi[k] = trim(p);
   }
 
   // ---- beta_k = alpha_k / (dt^{k-1} tau_k), zero where alpha_k = 0 ----
   qf beta[7] = {0};
   for (int k = 2; k <= 6; ++k) {
-    if (k > m || d.alpha[k] == 0.0 || Pi[k].empty()) continue;
+    if (k > m || d.alpha[k] == 0.0 || gPi[k].t.empty()) continue;
     if (qabs(tk[k]) < kSingular) return LBM_ERR_SINGULAR_TAU;
     qf dtp = 1;
     for (int i = 0; i < k - 1; ++i) dtp *= dt;
@@ -246,43 +471,31 @@ lbm_status build_model(const lbm_desc& d, Model* out) {
     }
   }
 
-  // ---- auxiliary moments Pi_k0 = int_0^phi I_k, k = 2..q-1 ----
-  const QPoly d1 = deriv(Pi[1]);
-  QPoly d1pow[7];
-  for (int p = 0; p <= 6; ++p) d1pow[p] = power(d1, p);
-  QPoly Pi0[7];
-  for (int k = 2; k < q; ++k) {
-    QPoly I = d1pow[k];
-    for (int r = 2; r <= k - 1; ++r) {
-      QPoly lead = scale(deriv(Pi[r]), beta[r]);
-      if (corrected && (r == 4 || r == 5)) lead = add(lead, QPoly{A[r]});
-      I = add(I, scale(mul(lead, d1pow[k - r]), (qf)binom(k, r)));
-    }
-    if (k >= 4) I = add(I, QPoly{A[k]});
-    Pi0[k] = antideriv(I);
-  }
-
-  // ---- scaled moments Pi_bar_k (Sec. III.A/B) ----
-  QPoly Pbar[kMaxQ];
-  Pbar[0] = QPoly{0, 1};
-  Pbar[1] = scale(Pi[1], 1 / c);
-  qf ck = c;
-  for (int k = 2; k < q; ++k) {
-    ck *= c;
-    Pbar[k] = scale(add(Pi0[k], scale(Pi[k], beta[k])), 1 / ck);
-  }
-  if (mdl.scheme == 2) Pbar[q - 1].clear();
-
-  // ---- collapse f_eq = M_q^{-1} Pi_bar into polynomials in phi ----
   qf inv[kMaxQ][kMaxQ];
   if (!invert_moment_matrix(q, inv)) return LBM_ERR_INVALID_ARG;
+  const qf omega = 1 / tau;
+  mdl.w0 = (double)(1 - omega);
+  if (general) {
+    if (d.prec == LBM_F32_DEV_ARITH32) return LBM_ERR_UNSUPPORTED;
+    GPoly Pbar[kMaxQ];
+    scaled_moments(gPi, beta, A, corrected, q, c, mdl.scheme, Pbar);
+    lbm_status st = collapse_general(Pbar, inv, q, omega, &mdl);
+    if (st != LBM_OK) return st;
+    set_rest_state(&mdl, 0.0);
+    *out = mdl;
+    return LBM_OK;
+  }
+
+  // ---- auxiliary moments and scaled moments (Sec. II.C-F, III.A/B) ----
+  QPoly Pbar[kMaxQ];
+  scaled_moments(Pi, beta, A, corrected, q, c, mdl.scheme, Pbar);
+
+  // ---- collapse f_eq = M_q^{-1} Pi_bar into polynomials in phi ----
   int D = 1;
   for (int k = 0; k < q; ++k)
     if ((int)Pbar[k].size() - 1 > D) D = (int)Pbar[k].size() - 1;
   if (D > kMaxDeg) return LBM_ERR_UNSUPPORTED;
   mdl.D = D;
-  const qf omega = 1 / tau;
-  mdl.w0 = (double)(1 - omega);
   for (int j = 0; j < q; ++j) {
     for (int p = 0; p <= D; ++p) {
       qf g = 0;
@@ -303,6 +516,14 @@ void set_rest_state(Model* mdl, double phi_rest) {
   const qf r = phi_rest;
   const qf omega = 1 / (qf)mdl->tau;
   mdl->phi_rest = phi_rest;
+  if (mdl->gF > 0) {   // power sums: f_rest only (the relaxation stays in phi)
+    for (int j = 0; j < mdl->q; ++j) {
+      const long double h = general_feq(*mdl, j, (long double)phi_rest);
+      mdl->f_rest[j] = (double)h;
+      mdl->wfrest[j] = (double)((long double)omega * h);
+    }
+    return;
+  }
   for (int j = 0; j < mdl->q; ++j) {
     // Taylor shift: f_eq_j(r + delta) = sum_p H[j][p] delta^p, H[j][p] = sum_k C(k,p) G[j][k] r^{k-p}
     for (int p = 0; p <= mdl->D; ++p) {
@@ -407,7 +628,11 @@ double stability_growth(const Model& m, double phi_min, double phi_max) {
     long double w[kMaxQ];
     for (int j = 0; j < m.q; ++j) {   // w_j = d/dphi sum_d G[j][d] phi^d at phi_bar
       long double acc = 0;
-      for (int d = m.D; d >= 1; --d) acc = acc * pb + (long double)d * (long double)m.Gq[j][d];
+      if (m.gF > 0) {
+        acc = general_dfeq(m, j, pb);
+      } else {
+        for (int d = m.D; d >= 1; --d) acc = acc * pb + (long double)d * (long double)m.Gq[j][d];
+      }
       w[j] = acc;
     }
     for (int k = 1; k < nk; ++k) {

@@ -13,6 +13,8 @@ namespace lbm {
 
 constexpr int kMaxQ = 7;
 constexpr int kMaxDeg = 19;   // Pi_1 of degree 4: (Pi_1')^6 has degree 18, Pi_60 degree 19
+constexpr int kGClasses = 4;  // non-polynomial Pi: distinct fractional parts of the exponents
+constexpr int kGDeg = 11;     // non-polynomial Pi: integer degree within one class
 
 struct Model {
   int q = 5;
@@ -36,7 +38,21 @@ struct Model {
   double wH[kMaxQ][kMaxDeg + 1] = {};
   // the 113-bit table, kept for the rest-state shift
   __float128 Gq[kMaxQ][kMaxDeg + 1] = {};
+  // Non-polynomial Pi (real exponents, Sec. III.C families with real n, p, q):
+  // f_eq_j(phi) = sum_c phi^gnu[c] sum_d gG[c][j][d] phi^d, gnu[0] = 0 and
+  // gnu[c] in (0, 1) the distinct fractional parts; G above is unused then
+  int gF = 0;                  // number of classes; 0 = polynomial model
+  double gnu[kGClasses] = {};
+  double gG[kGClasses][kMaxQ][kGDeg + 1] = {};
+  double gwG[kGClasses][kMaxQ][kGDeg + 1] = {};   // omega * gG
+  __float128 gGq[kGClasses][kMaxQ][kGDeg + 1] = {};
+  __float128 gnuq[kGClasses] = {};
 };
+
+// f_eq_j(phi) of a non-polynomial model in long double (host checks, rest state)
+long double general_feq(const Model& m, int j, long double phi);
+// d f_eq_j / d phi of a non-polynomial model (phi > 0)
+long double general_dfeq(const Model& m, int j, long double phi);
 
 // Validates the descriptor and builds the model; changes nothing on failure.
 lbm_status build_model(const lbm_desc& d, Model* out);

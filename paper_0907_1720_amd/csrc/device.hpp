@@ -8,6 +8,8 @@
 namespace lbm {
 
 constexpr int kRow = 20;   // coefficient row length (max degree 19 + 1)
+constexpr int kGRow = 12;  // power-sum tables: integer degree <= 11 per class
+constexpr int kGCls = 4;   // power-sum tables: fractional-power classes
 
 // Per-problem constants on the device.
 struct DevCoef {
@@ -21,6 +23,14 @@ struct DevCoef {
   float w0f;
   float pad_[3];
   float wHf[8][kRow];        // FP32 relaxation: omega * H[j][d], H = G shifted to the rest state
+  // Equilibria with real (non-integer) powers of phi (variant parity 2):
+  //   f_eq_j(phi) = sum_{c < gF} phi^gnu[c] sum_d G[c][j][d] phi^d
+  int32_t gF;                // classes; 0 for polynomial equilibria
+  int32_t gpad_;
+  double gnu[kGCls];         // gnu[0] = 0, the rest the fractional parts of the exponents
+  double grest[8];           // f_rest_j subtracted at initialisation (FP32 deviations), else 0
+  double gwc[kGCls][7][kGRow];    // omega * G
+  double ginit[kGCls][7][kGRow];  // G
 };
 
 // Resident path: a job is the set of instances one workgroup advances side by
@@ -102,6 +112,9 @@ __host__ __device__ constexpr int opposite(int j) {
 //        of G to the rest state (H[j][0] = 0)
 // Parity P = 1 marks equilibria that are odd in phi (every kept degree odd,
 // e.g. mKdV): coefficient k belongs to degree 2k+1 and Horner runs in phi^2.
+// P = 2 marks equilibria with real powers of phi (power sums, in FP64 with
+// phi^nu = exp2(nu log2 phi), phi >= 0; FP32 storage relaxes in phi itself and
+// adds -omega f_rest like the odd tables).
 __device__ __forceinline__ double fma_a(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_a(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -130,6 +143,7 @@ struct Relaxer {
   static constexpr int K = P == 0 ? D + 1 : (D + 1) / 2;   // coefficients per population
   static constexpr bool kRest = (sizeof(T) == 4 && sizeof(A) == 8);
   const A* __restrict__ c;   // [Q][kRow]: dense, or the odd degrees compacted
+  const DevCoef* __restrict__ cfp;   // power-sum tables (P = 2)
   A top[Q];
   A w0;
   double s0;                 // phi_rest (odd tables with FP32 storage)
@@ -137,23 +151,56 @@ struct Relaxer {
 
   __device__ __forceinline__ void init(const A* __restrict__ coef, A w0_, const DevCoef* __restrict__ cf) {
     c = coef;
+    cfp = cf;
     w0 = w0_;
     s0 = cf->s0;
     cst = cf->cst;
+    if constexpr (P != 2) {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      top[j] = c[j * kRow + K - 1];
-      asm volatile("" : "+v"(top[j]));
+      for (int j = 0; j < Q; ++j) {
+        top[j] = c[j * kRow + K - 1];
+        asm volatile("" : "+v"(top[j]));
+      }
     }
   }
 
   __device__ __forceinline__ void operator()(T (&f)[Q]) const {
     double s = (double)f[0];
-    if constexpr (kRest && P == 1) s = s0 + s;
+    if constexpr ((kRest && P == 1) || (sizeof(T) == 4 && P == 2)) s = s0 + s;
 #pragma unroll
     for (int j = 1; j < Q; ++j) s += (double)f[j];
     const A p = (A)s;
-    if constexpr (P == 0) {
+    if constexpr (P == 2) {
+      const DevCoef* __restrict__ g = cfp;
+      const double lg = log2(s);
+      double acc[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        double a = g->gwc[0][j][D];
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) a = __builtin_fma(a, s, g->gwc[0][j][d]);
+        acc[j] = a;
+      }
+      const int F = g->gF;
+#pragma unroll
+      for (int cl = 1; cl < kGCls; ++cl) {
+        if (cl < F) {
+          const double sc = exp2(g->gnu[cl] * lg);
+#pragma unroll
+          for (int j = 0; j < Q; ++j) {
+            double a = g->gwc[cl][j][D];
+#pragma unroll
+            for (int d = D - 1; d >= 0; --d) a = __builtin_fma(a, s, g->gwc[cl][j][d]);
+            acc[j] = __builtin_fma(sc, a, acc[j]);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const double add = sizeof(T) == 4 ? cst[j] : 0.0;
+        f[j] = (T)__builtin_fma((double)w0, (double)f[j], acc[j] + add);
+      }
+    } else if constexpr (P == 0) {
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
         A acc = top[j];

@@ -20,11 +20,29 @@ namespace lbm {
 // ---------------------------------------------------------------------------
 // f := f_eq(phi)
 // ---------------------------------------------------------------------------
+// stored equilibrium of a power-sum model: f_eq_j(phi) - f_rest_j (f_rest = 0
+// for FP64 storage); phi >= 0
+__device__ __forceinline__ double general_stored_eq(const DevCoef* __restrict__ cf, int j, double phi) {
+  const double lg = log2(phi);
+  double acc = 0.0;
+  for (int c = 0; c < cf->gF; ++c) {
+    double a = cf->ginit[c][j][kGRow - 1];
+    for (int d = kGRow - 2; d >= 0; --d) a = __builtin_fma(a, phi, cf->ginit[c][j][d]);
+    acc = __builtin_fma(c == 0 ? 1.0 : exp2(cf->gnu[c] * lg), a, acc);
+  }
+  return acc - cf->grest[j];
+}
+
 template <int Q, int D, typename T>
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi, T* __restrict__ f,
                                               int n, int stride, const DevCoef* __restrict__ cf) {
   const int x = blockIdx.x * 256 + threadIdx.x;
   if (x >= n) return;
+  if (cf->gF > 0) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) f[(int64_t)j * stride + x] = (T)general_stored_eq(cf, j, phi[x]);
+    return;
+  }
   const double p = phi[x] - cf->phi_rest;   // phi_rest = 0 for FP64 storage
 #pragma unroll
   for (int j = 0; j < Q; ++j) f[(int64_t)j * stride + x] = (T)poly_eval<D, 0, double>(cf->init[j], p);
@@ -59,11 +77,14 @@ __global__ __launch_bounds__(64) void k_bound(T* __restrict__ f, int n, int stri
     }
     // s = phi - phi_rest (phi itself for FP64 storage)
 #pragma unroll
-    for (int j = 0; j < Q; ++j) neq[j] = g[j] - poly_eval<D, 0, double>(cf->init[j], s);
+    for (int j = 0; j < Q; ++j)
+      neq[j] = g[j] - (cf->gF > 0 ? general_stored_eq(cf, j, s + cf->phi_rest) : poly_eval<D, 0, double>(cf->init[j], s));
   }
   const double p = phib[t] - cf->phi_rest;
 #pragma unroll
-  for (int j = 0; j < Q; ++j) f[(int64_t)j * stride + x] = (T)(poly_eval<D, 0, double>(cf->init[j], p) + neq[j]);
+  for (int j = 0; j < Q; ++j)
+    f[(int64_t)j * stride + x] =
+        (T)((cf->gF > 0 ? general_stored_eq(cf, j, phib[t]) : poly_eval<D, 0, double>(cf->init[j], p)) + neq[j]);
 }
 
 // ---------------------------------------------------------------------------
@@ -268,6 +289,7 @@ __device__ void resident_job(T* __restrict__ L, int steps, const DevJobInst& ji,
 // compiled for eight waves per SIMD, the others without a bound.
 template <int Q, int D, int P, typename A>
 constexpr int resident_waves_per_simd() {
+  if constexpr (P == 2) return 1;
   if constexpr (sizeof(A) == 4) return 8;
   if constexpr (Q <= 5) return (P ? D <= 9 : D <= 5) ? 8 : 1;
   return 1;

@@ -157,6 +157,28 @@ void fill_devcoef(const HostInst& h, DevCoef* c) {
   const int parity = h.D >> 8;
   c->w0 = m.w0;
   c->w0f = (float)m.w0;
+  if (m.gF > 0) {
+    // power sums: omega * G and G per class; FP32 deviations relax in phi
+    // = phi_rest + sum_j g_j and add -omega f_rest
+    c->gF = m.gF;
+    for (int cl = 0; cl < m.gF; ++cl) {
+      c->gnu[cl] = m.gnu[cl];
+      for (int j = 0; j < m.q; ++j)
+        for (int d = 0; d <= kGDeg && d < kGRow; ++d) {
+          c->gwc[cl][j][d] = m.gwG[cl][j][d];
+          c->ginit[cl][j][d] = m.gG[cl][j][d];
+        }
+    }
+    if (h.f32) {
+      c->phi_rest = m.phi_rest;
+      c->s0 = m.phi_rest;
+      for (int j = 0; j < m.q; ++j) {
+        c->cst[j] = -m.wfrest[j];
+        c->grest[j] = m.f_rest[j];
+      }
+    }
+    return;
+  }
   // FP64 relaxation table: omega * G over the kept degrees
   for (int j = 0; j < m.q; ++j) {
     if (parity == 0) {
@@ -256,13 +278,14 @@ lbm_status prepare_one(const lbm_desc& d, HostInst* hp) {
   h.f32 = h.prec != LBM_F64;
   // odd equilibria (every degree with a nonzero coefficient is odd) evaluate in phi^2;
   // the FP32 relaxation uses the shifted (dense) table
-  bool odd = h.prec != LBM_F32_DEV_ARITH32;
+  bool odd = h.prec != LBM_F32_DEV_ARITH32 && h.mdl.gF == 0;
   for (int j = 0; j < h.mdl.q && odd; ++j)
     for (int p = 0; p <= h.mdl.D; p += 2)
       if (h.mdl.G[j][p] != 0.0) odd = false;
-  const int parity = odd ? 1 : 0;
+  const int parity = h.mdl.gF > 0 ? 2 : (odd ? 1 : 0);
   const int kd = padded_degree(h.mdl.D, parity);
-  h.Dinit = padded_degree(h.mdl.D, 0);
+  // power sums initialise through their own tables; any init variant serves
+  h.Dinit = h.mdl.gF > 0 ? padded_degree(1, 0) : padded_degree(h.mdl.D, 0);
   if (kd == 0 || h.Dinit == 0) return LBM_ERR_UNSUPPORTED;
   h.D = variant_code(kd, parity);
   h.n = (int)d.n;
@@ -405,6 +428,9 @@ lbm_status load_phi_one(lbm_batch_s* b, int i, const double* phi, int on_device)
   }
   for (double v : host)
     if (!std::isfinite(v)) return LBM_ERR_INVALID_ARG;
+  if (h.mdl.gF > 1)   // real (non-integer) powers of phi need phi >= 0
+    for (double v : host)
+      if (v < 0) return LBM_ERR_INVALID_ARG;
   if (h.f32) {
     // rest state: the mean of phi0 (conserved on a periodic grid)
     long double s = 0;
@@ -1192,9 +1218,29 @@ lbm_status lbm_coefficients(const lbm_desc* d, double* G, int32_t cap, int32_t* 
   Model m;
   lbm_status s = build_model(*d, &m);
   if (s != LBM_OK) return s;
+  if (m.gF > 0) return LBM_ERR_UNSUPPORTED;   // not a polynomial in phi
   if (cap < m.q * (m.D + 1)) return LBM_ERR_INVALID_ARG;
   for (int j = 0; j < m.q; ++j)
     for (int p = 0; p <= m.D; ++p) G[j * (m.D + 1) + p] = m.G[j][p];
+  *q_out = m.q;
+  *degree_out = m.D;
+  return LBM_OK;
+}
+
+lbm_status lbm_coefficients_general(const lbm_desc* d, double* nu, double* G, int32_t cap, int32_t* classes_out,
+                                    int32_t* q_out, int32_t* degree_out) {
+  if (!d || !nu || !G || !classes_out || !q_out || !degree_out) return LBM_ERR_INVALID_ARG;
+  Model m;
+  lbm_status s = build_model(*d, &m);
+  if (s != LBM_OK) return s;
+  const int F = m.gF > 0 ? m.gF : 1;
+  if (cap < F * m.q * (m.D + 1)) return LBM_ERR_INVALID_ARG;
+  for (int c = 0; c < F; ++c) {
+    nu[c] = m.gF > 0 ? m.gnu[c] : 0.0;
+    for (int j = 0; j < m.q; ++j)
+      for (int p = 0; p <= m.D; ++p) G[(c * m.q + j) * (m.D + 1) + p] = m.gF > 0 ? m.gG[c][j][p] : m.G[j][p];
+  }
+  *classes_out = F;
   *q_out = m.q;
   *degree_out = m.D;
   return LBM_OK;
@@ -1208,6 +1254,7 @@ lbm_status lbm_stability(const lbm_desc* d, double phi_min, double phi_max, int6
   Model m;
   lbm_status s = build_model(*d, &m);
   if (s != LBM_OK) return s;
+  if (m.gF > 1 && phi_min <= 0) return LBM_ERR_INVALID_ARG;   // real powers: phi > 0 only
   const double g = stability_growth(m, phi_min, phi_max);
   *growth_per_step = g;
   if (amplification) *amplification = std::pow(g, (double)steps);

@@ -38,6 +38,10 @@ class LbmDesc(ctypes.Structure):
         ("tau", ctypes.c_double),
         ("bc", ctypes.c_int32),
         ("prec", ctypes.c_int32),
+        ("pi_terms", ctypes.c_int32 * 7),
+        ("pi_pad_", ctypes.c_int32),
+        ("pi_gexp", (ctypes.c_double * 4) * 7),
+        ("pi_gcoef", (ctypes.c_double * 4) * 7),
     ]
 
 
@@ -80,6 +84,7 @@ def library() -> ctypes.CDLL:
         "lbm_row_stride": (I64, [I64]),
         "lbm_validate": (I32, [DP]),
         "lbm_coefficients": (I32, [DP, P, I32, P, P]),
+        "lbm_coefficients_general": (I32, [DP, P, P, I32, P, P, P]),
         "lbm_required_bytes": (I32, [DP, P]),
         "lbm_stability": (I32, [DP, D, D, I64, P, P]),
         "lbm_create": (I32, [DP, P, P, SZ, P]),
@@ -149,6 +154,17 @@ def make_desc(p: Problem) -> LbmDesc:
             d.pi_deg[k] = len(coeffs) - 1
             for i, c in enumerate(coeffs):
                 d.pi_coef[k][i] = float(c)
+    gpi = getattr(p, "gpi", ())
+    for k in range(1, 7):
+        terms = gpi[k] if k < len(gpi) else ()
+        if len(terms) == 0:
+            continue
+        if len(terms) > 4:
+            raise ValueError("at most 4 terms per non-polynomial Pi_k")
+        d.pi_terms[k] = len(terms)
+        for i, (e, c) in enumerate(terms):
+            d.pi_gexp[k][i] = float(e)
+            d.pi_gcoef[k][i] = float(c)
     d.n = int(p.n)
     d.dx, d.dt, d.tau = float(p.dx), float(p.dt), float(p.tau)
     d.bc = int(getattr(p, "bc", 0))
@@ -167,6 +183,18 @@ def coefficients(p: Problem) -> np.ndarray:
     _check(library().lbm_coefficients(ctypes.byref(make_desc(p)), buf.ctypes.data, buf.size,
                                       ctypes.byref(q), ctypes.byref(D)), "lbm_coefficients")
     return buf[: q.value * (D.value + 1)].reshape(q.value, D.value + 1).copy()
+
+
+def coefficients_general(p: Problem):
+    """(nu, G) with f_eq_j(phi) = sum_c phi^nu[c] sum_d G[c, j, d] phi^d (every model)."""
+    nu = np.zeros(4, dtype=np.float64)
+    buf = np.zeros(4 * 7 * 20, dtype=np.float64)
+    F, q, D = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(library().lbm_coefficients_general(ctypes.byref(make_desc(p)), nu.ctypes.data, buf.ctypes.data, buf.size,
+                                              ctypes.byref(F), ctypes.byref(q), ctypes.byref(D)),
+           "lbm_coefficients_general")
+    n = F.value * q.value * (D.value + 1)
+    return nu[: F.value].copy(), buf[:n].reshape(F.value, q.value, D.value + 1).copy()
 
 
 def stability(p: Problem, phi_min: float, phi_max: float, steps: int):

@@ -135,3 +135,69 @@ def test_required_bytes():
     assert lbm.Solver.required_bytes(p) == 5 * 128 * 8
     p32 = dataclasses.replace(W.kawahara(100, 0.0586, 1.3e-5, 3.0, 0.0), prec=W.F32_DEV)
     assert lbm.Solver.required_bytes(p32) == 7 * 128 * 4
+
+
+POWER_PROBLEMS = {
+    "power_kdv_1.5": W.power_kdv(1.5, 0.01, 64, 0.1, 1e-3, 2.0, 0.0, nu=0.05),
+    "power_kdv_0.5_q4": W.power_kdv(0.5, 0.02, 64, 0.1, 0.01, 2.0, 0.0, nu=3.0, q=4),
+    "family_b": W.family_b(0.5, 0.75, 0.5, -0.05, 1.5, 0.01, 2.5, 64, 0.1, 1e-3, 2.0, 0.0),
+    "family_a_q7": W.family_a(0.5, 0.5, 1.5, (-0.05, 0.01, 1e-4, 0.0, 0.0), 64, 0.1, 1e-3, 2.0, 0.0, q=7),
+    "family_a_q7_am": W.family_a(0.5, 0.5, 1.5, (-0.05, 0.01, 1e-4, -1e-5, 2e-6), 64, 0.1, 1e-3, 2.0, 0.0,
+                                 q=7, am=1),
+    "family_a_third": W.family_a(0.0, 1.0, 1.0 / 3.0, (-3.0, 1e-3, 0.0625, -1e-3, 0.0), 64, 0.1, 0.01, 2.0,
+                                 0.0, q=6),
+}
+
+
+@pytest.mark.parametrize("name", sorted(POWER_PROBLEMS))
+def test_power_sum_equilibrium_matches_oracle(name):
+    p = POWER_PROBLEMS[name]
+    nu, G = lbm.coefficients_general(p)
+    mdl = O.build_model(p)
+    assert mdl.general and G.shape[1] == mdl.q and nu[0] == 0.0 and len(nu) > 1
+    phi = np.linspace(0.02, 3.0, 101)
+    want = O.equilibrium(mdl, phi)
+    powers = phi[None, :] ** np.arange(G.shape[2])[:, None]
+    got = np.zeros_like(want)
+    scale = np.abs(want).copy()
+    for c in range(len(nu)):
+        term = (phi ** nu[c])[None, :] * (G[c] @ powers)
+        got += term
+        scale += (phi ** nu[c])[None, :] * (np.abs(G[c]) @ np.abs(powers))
+    assert np.max(np.abs(got - want) / scale) < 1e-13
+    # the polynomial-only entry point refuses such models
+    assert lib_status(lambda lib, d: lib.lbm_coefficients(ctypes.byref(d), np.zeros(400).ctypes.data, 400,
+                                                          ctypes.byref(ctypes.c_int32()),
+                                                          ctypes.byref(ctypes.c_int32())), p) == lbm.UNSUPPORTED
+
+
+def lib_status(call, p):
+    return call(lbm.library(), lbm.make_desc(p))
+
+
+def test_polynomial_model_through_the_general_entry_point():
+    p = PROBLEMS["kawahara"]
+    nu, G = lbm.coefficients_general(p)
+    assert list(nu) == [0.0]
+    assert np.array_equal(G[0], lbm.coefficients(p))
+
+
+def test_power_sum_validation():
+    good = POWER_PROBLEMS["power_kdv_1.5"]
+    assert lbm.validate(good) == lbm.OK
+    bad_exp = dataclasses.replace(good, gpi=((), ((0.5, 1.0),)) + ((),) * 5)      # exponent in (0, 1)
+    assert lbm.validate(bad_exp) == lbm.INVALID_ARG
+    big = dataclasses.replace(good, gpi=((), ((8.5, 1.0),)) + ((),) * 5)          # exponent > 8
+    assert lbm.validate(big) == lbm.INVALID_ARG
+    many = dataclasses.replace(good, gpi=((), ((1.1, 1.0), (1.2, 1.0), (1.3, 1.0), (1.7, 0.5))) + ((),) * 5)
+    assert lbm.validate(many) == lbm.UNSUPPORTED                                   # > 4 fractional classes
+    assert lbm.validate(dataclasses.replace(good, prec=W.F32_DEV)) == lbm.OK
+    assert lbm.validate(dataclasses.replace(good, prec=W.F32_DEV_ARITH32)) == lbm.UNSUPPORTED
+    with pytest.raises(lbm.LBMError):
+        lbm.stability(good, 0.0, 1.0, 10)      # real powers: phi_min must be > 0
+    g, _ = lbm.stability(good, 0.5, 1.5, 10)
+    assert 0.9 < g < 1.1
+    # integer exponents given as real powers are the polynomial model
+    as_int = W.family_b(0.5, 0.75, 2.0, -0.25, 1.0, 0.5, 2.0, 64, 0.25, 0.015625, 1.25, 0.0, q=5)
+    nu, G = lbm.coefficients_general(as_int)
+    assert list(nu) == [0.0]
