@@ -22,11 +22,17 @@ Reported:
   serving               p50/p99 latency and throughput of a Poisson stream of
                         mixed solve requests through the continuous-batching server
   autotune              the planner settings the autotuner kept for each batch
+  next_rows             the extensions beyond the periodic batch, each timed on the
+                        device: the bounded Table VIII example as a 64-tau sweep
+                        in one batch (resident, boundary layers reset in LDS) and
+                        on the per-step streaming path; real-power equilibria;
+                        the D1Q4 / D1Q6 lattices
   cpu_baseline          the CPU oracle on a sample of the same instances
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import multiprocessing as mp
@@ -46,7 +52,7 @@ COUNT = 4096
 LB_STEPS = 5000
 PEAK_VALU_TFLOPS = 78.6      # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 flop/FMA (FP64 = non-packed FP32)
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_counters_kdv_mkdv_batch4096.md")
-KERNEL_SOURCES = ("kernels.hip", "device.hpp", "kernels.hpp", "runtime.cpp")
+KERNEL_SOURCES = ("kernels_body.hpp", "kernels_q.hip", "kernels.hip", "device.hpp", "kernels.hpp", "runtime.cpp")
 
 
 def kernel_source_digest() -> str:
@@ -127,6 +133,8 @@ def main():
                     help="time only the HBM-streaming path on one large grid (for profiler runs)")
     ap.add_argument("--large-only", action="store_true",
                     help="time only the large-grid workloads (for profiler runs); prints a reduced line")
+    ap.add_argument("--next-only", action="store_true",
+                    help="time only the extension workloads (bounded sweep, real powers, D1Q4/D1Q6)")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the FP32 batch (for profiler runs); prints a reduced line")
     args = ap.parse_args()
@@ -231,6 +239,80 @@ def main():
             s.close()
         return out
 
+    def timed_batch(insts, steps, label):
+        """Device rate of one pass (after a warm-up pass) of a periodic batch."""
+        b = lbm.Batch([x.problem for x in insts], stream=stream.cuda_stream)
+        b.load_phi([x.phi0 for x in insts])
+        b.advance(steps)
+        torch.cuda.synchronize()
+        b.advance(steps)
+        ms = b.last_advance_ms()
+        ok = all(b.read_phi(i)[1] == lbm.OK for i in range(len(insts)))
+        b.close()
+        nu = sum(x.problem.n for x in insts) * steps
+        out = {"workload": label, "instances": len(insts), "steps": steps, "node_updates": nu,
+               "kernel_ms": ms, "node_updates_per_s": nu / (ms * 1e-3), "status_ok": ok}
+        try:
+            fl = sum(x.problem.n * steps * algorithmic_flops_per_nu(lbm.coefficients(x.problem)) for x in insts)
+            out["alu_frac"] = fl / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS
+        except lbm.LBMError:   # real powers: no polynomial table (flops of exp2/log2 are not counted)
+            pass
+        return out
+
+    def next_rows():
+        out = {}
+        # bounded (Sec. IV boundaries) x tau sweep: Table VIII to t = 150 at 64 taus
+        p0, x, ex = W.table8_bounded()
+        steps, layers = 15000, 2
+        xb = np.concatenate([x[:layers], x[-layers:]])
+        phib = np.stack([ex(xb, s * p0.dt) for s in range(1, steps + 1)])
+        taus = np.linspace(0.97, 2.5, 64)
+        probs = [dataclasses.replace(p0, tau=float(t)) for t in taus]
+        b = lbm.Batch(probs, stream=stream.cuda_stream)
+        b.load_phi([ex(x, 0.0)] * len(probs))
+        b.advance_bounded([phib[:200]] * len(probs))            # warm-up
+        b.load_phi([ex(x, 0.0)] * len(probs))
+        b.advance_bounded([phib] * len(probs))
+        ms = b.last_advance_ms()
+        res = [b.read_phi(i) for i in range(len(probs))]
+        b.close()
+        err = [float(np.sum(np.abs(r[0] - ex(x, steps * p0.dt))) / np.sum(np.abs(ex(x, steps * p0.dt))))
+               if r[1] == lbm.OK else float("inf") for r in res]
+        nu = len(probs) * p0.n * steps
+        fl = nu * algorithmic_flops_per_nu(lbm.coefficients(p0))
+        out["bounded_tau_sweep"] = {
+            "workload": "Table VIII KdV-Burgers on [-4, 4] (801 nodes, D1Q5, NEE boundaries), 64 taus in "
+                        "[0.97, 2.5], 15000 steps (t = 150) in one batch",
+            "node_updates": nu, "kernel_ms": ms, "node_updates_per_s": nu / (ms * 1e-3),
+            "alu_frac": fl / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
+            "tau_opt": float(taus[int(np.argmin(err))]), "E_at_tau_opt": float(min(err)),
+            "status_ok": all(r[1] == lbm.OK for r in res)}
+        # the same problem on the per-step streaming path (one collide+stream and
+        # one boundary launch per step)
+        s = lbm.Solver(p0, stream=stream.cuda_stream)
+        s.set_path(lbm.PATH_STREAM)
+        s.load_phi(ex(x, 0.0))
+        s.advance_bounded(phib[:200])
+        torch.cuda.synchronize()
+        s.advance_bounded(phib[200:2200])
+        ms1 = s.last_advance_ms()
+        s.close()
+        out["bounded_streaming_single"] = {"workload": "the same problem at tau = 0.97, 2000 steps, one instance",
+                                           "kernel_ms": ms1, "node_updates_per_s": p0.n * 2000 / (ms1 * 1e-3)}
+        out["real_powers"] = timed_batch([W.power_batch_instance(i) for i in range(1024)], 2000,
+                                         "1024 periodic phi_t + phi^n phi_x + delta phi_xxx = 0, n in {0.5, 1.5}, "
+                                         "N log-uniform [256, 4096], FP64, D1Q5")
+        out["real_powers_fp32"] = timed_batch([W.power_batch_instance(i, prec=W.F32_DEV) for i in range(1024)],
+                                              2000, "the same, FP32 deviation storage")
+        out["d1q4"] = timed_batch([W.even_lattice_instance(i, 4) for i in range(1024)], 2000,
+                                  "1024 D1Q4 KdV-Burgers, N log-uniform [256, 4096], FP64")
+        out["d1q6"] = timed_batch([W.even_lattice_instance(i, 6) for i in range(1024)], 2000,
+                                  "1024 D1Q6 fifth-order dissipative equations, N log-uniform [256, 4096], FP64")
+        return out
+
+    if args.next_only:
+        print(json.dumps({"metric": "extensions (next rows) only", "next_rows": next_rows()}))
+        return
     if args.stream_only:
         print(json.dumps({"metric": "HBM streaming path", "hbm_stream": hbm_stream()}))
         return
@@ -246,6 +328,7 @@ def main():
     r64 = run(W.F64)
     lg = large_grids()
     hs = hbm_stream()
+    nx = next_rows()
 
     # plain FP64 path: one instance at a time, one launch per step
     sample = np.linspace(0, args.count - 1, args.plain_sample).astype(int)
@@ -315,6 +398,7 @@ def main():
         "large_grids": {"workload": "Kuramoto-Sivashinsky N = 8192 (256 instances, 640 steps) and "
                                     "Kawahara/K(2,2) N in {2048, 16384} (512 instances, 500 steps), device time",
                         **lg},
+        "next_rows": nx,
         "status_ok": bool(r32["status_ok"] and r64["status_ok"]),
         "roofline": roofline,
         "serving": {"requests": srv_out["requests"], "arrival_rate_per_s": srv_out["rate_per_s"],

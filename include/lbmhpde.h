@@ -171,9 +171,12 @@ lbm_status lbm_advance(lbm_problem h, int64_t steps);
    nodes 0..layers-1, k >= layers nodes n-layers..n-1, at time s dt after the
    steps already taken.  phib is a host array of steps * 2 * layers doubles,
    copied before the call returns.  layers = 0 means q/2; layers must lie in
-   [q/2, 32] and n >= 2 layers + 2.  Each step is one fused collide+stream
-   launch through HBM plus one boundary launch.  INVALID_ARG for a periodic
-   problem or bad sizes. */
+   [q/2, 32] and n >= 2 layers + 2.  A state that fits one workgroup's LDS
+   advances on the resident path (the layers reset in LDS after every step;
+   steps <= 2^30), otherwise -- or with lbm_set_path(LBM path 1) -- each step
+   is one fused collide+stream launch through HBM plus one boundary launch;
+   both give bitwise equal results.  INVALID_ARG for a periodic problem or bad
+   sizes. */
 lbm_status lbm_advance_bounded(lbm_problem h, int64_t steps, const double* phib, int32_t layers);
 
 /* phi = sum_j f_j (zeroth moment, FP64) into n doubles on the host or device.
@@ -221,6 +224,16 @@ lbm_status lbm_batch_load_phi(lbm_batch b, const double* const* phi0);
 /* Advance instance i by steps[i] (>= 0) steps, all instances in persistent
    launches; asynchronous.  steps == NULL advances nothing. */
 lbm_status lbm_batch_advance(lbm_batch b, const int64_t* steps);
+/* Bounded instances of a batch (Sec. IV boundaries, as lbm_advance_bounded):
+   every instance advances `steps` (<= 2^30) steps; bounded instance i resets
+   its `layers` outer nodes at each end after every step from phib[i] (host,
+   steps * 2 * layers doubles, copied before the call returns; ignored and may
+   be NULL for periodic instances).  layers = 0 means the largest q/2 of the
+   bounded instances; layers in [that, 32], n >= 2 layers + 2.  Bounded
+   instances run on the LDS-resident path: LBM_ERR_UNSUPPORTED if one does not
+   fit a workgroup's LDS or another path is forced.  A tau sweep of one bounded
+   problem is one call. */
+lbm_status lbm_batch_advance_bounded(lbm_batch b, int64_t steps, const double* const* phib, int32_t layers);
 
 /* phi of instance i into n host doubles; *inst_status (nullable) receives
    LBM_OK or LBM_ERR_NONFINITE for that instance alone.  Synchronises. */

@@ -12,6 +12,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -40,18 +41,30 @@ def _run(cmd):
     return out
 
 
+LATTICES = (4, 5, 6, 7)
+
+
 def build(verbose: bool = False) -> str:
+    """Compiles the host sources, the read-out/launcher unit and one kernel unit
+    per lattice size (kernels_q.hip with LBM_Q = 4..7) in parallel, then links."""
     os.makedirs(BUILD, exist_ok=True)
     inc = [f"-I{INCLUDE}", f"-I{CSRC}"]
-    objs = []
+    steps = []
     for src in ("coeffs.cpp", "runtime.cpp"):
         obj = os.path.join(BUILD, src + ".o")
-        _run([CLANG] + HOST_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
-    for src in ("kernels.hip",):
-        obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC] + DEVICE_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        steps.append((obj, [CLANG] + HOST_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj]))
+    obj = os.path.join(BUILD, "kernels.hip.o")
+    steps.append((obj, [HIPCC] + DEVICE_FLAGS + inc + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", obj]))
+    for q in LATTICES:
+        obj = os.path.join(BUILD, f"kernels_q{q}.hip.o")
+        steps.append((obj, [HIPCC] + DEVICE_FLAGS + inc + [f"-DLBM_Q={q}", "-c",
+                                                            os.path.join(CSRC, "kernels_q.hip"), "-o", obj]))
+    # the D1Q7 and D1Q5 units take longest: start them first
+    steps.sort(key=lambda st: ("q7" not in st[0], "q5" not in st[0]))
+    jobs = max(1, min(len(steps), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(jobs) as pool:
+        list(pool.map(lambda st: _run(st[1]), steps))
+    objs = [st[0] for st in steps]
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs)
     os.replace(tmp, LIB)

@@ -26,7 +26,7 @@ struct DevCoef {
   // Equilibria with real (non-integer) powers of phi (variant parity 2):
   //   f_eq_j(phi) = sum_{c < gF} phi^gnu[c] sum_d G[c][j][d] phi^d
   int32_t gF;                // classes; 0 for polynomial equilibria
-  int32_t gpad_;
+  int32_t groots;            // 1: every gnu is 1/2, 1/4 or 3/4 (square roots suffice, no log2)
   double gnu[kGCls];         // gnu[0] = 0, the rest the fractional parts of the exponents
   double grest[8];           // f_rest_j subtracted at initialisation (FP32 deviations), else 0
   double gwc[kGCls][7][kGRow];    // omega * G
@@ -41,9 +41,13 @@ struct DevJob {
   int32_t count;             // instances in the job (<= 16)
   int32_t steps;             // steps of this launch
   int32_t degree;            // kernel variant shared by all instances of the job
+  int32_t bounded;           // 1: the instances reset their boundary layers after every step
+  int32_t pad_;
 };
 struct DevJobInst {
   uint64_t addr;             // device address of row 0 of the instance's current state
+  uint64_t phib;             // bounded: device address of phi* at the outer layers for the
+                             // launch's first step, [steps][2 layers] (left, then right); else 0
   int32_t n;                 // nodes
   int32_t stride;            // row stride in elements
   int32_t degree;            // kernel variant: padded degree D | (parity << 8)
@@ -51,6 +55,8 @@ struct DevJobInst {
   int32_t lds_off;           // element offset of the instance's LDS region
   int32_t t0;                // first thread (multiple of 64)
   int32_t nt;                // threads (multiple of 64)
+  int32_t bkind;             // 0 periodic, 1 equilibrium layers, 2 non-equilibrium extrapolation
+  int32_t layers;            // boundary layers at each end (bounded)
   int32_t pad_;
 };
 
@@ -113,8 +119,9 @@ __host__ __device__ constexpr int opposite(int j) {
 // Parity P = 1 marks equilibria that are odd in phi (every kept degree odd,
 // e.g. mKdV): coefficient k belongs to degree 2k+1 and Horner runs in phi^2.
 // P = 2 marks equilibria with real powers of phi (power sums, in FP64 with
-// phi^nu = exp2(nu log2 phi), phi >= 0; FP32 storage relaxes in phi itself and
-// adds -omega f_rest like the odd tables).
+// phi^nu from square roots when every nu is 1/2, 1/4 or 3/4, else
+// exp2(nu log2 phi); phi >= 0; FP32 storage relaxes in phi itself and adds
+// -omega f_rest like the odd tables).
 __device__ __forceinline__ double fma_a(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_a(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -138,6 +145,18 @@ __device__ __forceinline__ A poly_eval(const A* __restrict__ c, A p) {
 // Per-thread relaxation constants.  The leading coefficient of each
 // polynomial is pinned to a VGPR so that every Horner step is a single FMA
 // with at most one scalar operand.
+// phi^nu for a fractional class: the square roots for nu = 1/2, 1/4, 3/4
+// (correctly rounded, a few instructions), else exp2(nu log2 phi); phi >= 0
+__device__ __forceinline__ double frac_pow(double nu, double phi, double lg, bool roots) {
+  if (roots) {
+    const double r = __builtin_sqrt(phi);
+    if (nu == 0.5) return r;
+    const double r4 = __builtin_sqrt(r);
+    return nu == 0.25 ? r4 : r * r4;
+  }
+  return exp2(nu * lg);
+}
+
 template <int Q, int D, int P, typename T, typename A>
 struct Relaxer {
   static constexpr int K = P == 0 ? D + 1 : (D + 1) / 2;   // coefficients per population
@@ -172,7 +191,8 @@ struct Relaxer {
     const A p = (A)s;
     if constexpr (P == 2) {
       const DevCoef* __restrict__ g = cfp;
-      const double lg = log2(s);
+      const bool roots = g->groots != 0;
+      const double lg = roots ? 0.0 : log2(s);
       double acc[Q];
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
@@ -185,7 +205,7 @@ struct Relaxer {
 #pragma unroll
       for (int cl = 1; cl < kGCls; ++cl) {
         if (cl < F) {
-          const double sc = exp2(g->gnu[cl] * lg);
+          const double sc = frac_pow(g->gnu[cl], s, lg, roots);
 #pragma unroll
           for (int j = 0; j < Q; ++j) {
             double a = g->gwc[cl][j][D];

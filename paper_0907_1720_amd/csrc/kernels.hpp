@@ -72,7 +72,9 @@ hipError_t launch_stream(int q, int code, int prec, const void* fin, void* fout,
 // graph nodes; nullptr for an unknown variant
 const void* stream_kernel(int q, int code, int prec);
 // persistent launch over `njobs` jobs (bin-packed instances of one variant
-// `code`), each split into `nchunks` step chunks; done[0..njobs) starts at 0
+// `code`), each split into `nchunks` step chunks; done[0..njobs) starts at 0.
+// code | (1 << 16) selects the kernel of bounded jobs (boundary layers reset
+// in LDS after every step)
 hipError_t launch_resident(int q, int prec, int code, const DevJob* jobs, const DevJobInst* jinst, int njobs,
                            int nchunks, int* counter, int* slots, int* done, const DevCoef* coefs, int* status,
                            int grid, int block, size_t lds, hipStream_t s);

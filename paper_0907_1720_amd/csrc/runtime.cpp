@@ -143,6 +143,11 @@ struct lbm_batch_s {
   std::vector<StepGraph> step_graphs;   // per instance and current-buffer parity
   double* bound = nullptr;              // boundary values of bounded problems (device)
   size_t bound_cap = 0;                 // doubles
+  // a bounded advance in progress: phi* rows per instance (device address, 0
+  // for periodic instances) and the layers reset at each end
+  bool bnd_active = false;
+  int bnd_layers = 0;
+  std::vector<uint64_t> bnd_ptr;
 };
 
 struct lbm_problem_s {
@@ -161,6 +166,9 @@ void fill_devcoef(const HostInst& h, DevCoef* c) {
     // power sums: omega * G and G per class; FP32 deviations relax in phi
     // = phi_rest + sum_j g_j and add -omega f_rest
     c->gF = m.gF;
+    c->groots = 1;
+    for (int cl = 1; cl < m.gF; ++cl)
+      if (m.gnu[cl] != 0.5 && m.gnu[cl] != 0.25 && m.gnu[cl] != 0.75) c->groots = 0;
     for (int cl = 0; cl < m.gF; ++cl) {
       c->gnu[cl] = m.gnu[cl];
       for (int j = 0; j < m.q; ++j)
@@ -522,7 +530,8 @@ constexpr int kMaxChunks = 64;
 lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   const int count = (int)b->inst.size();
   // resident groups by (q, precision, variant); the rest streams through HBM
-  std::map<std::tuple<int, int, int>, std::vector<int>> res;   // (q, prec, variant code)
+  // (q, prec, variant code, bounded)
+  std::map<std::tuple<int, int, int, int>, std::vector<int>> res;
   std::vector<int> str;          // one launch per step (the plain path)
   std::vector<int> til[8][3];    // temporal blocking, by (q, prec)
   // slabs, by (q, prec, variant, workgroups per CU)
@@ -540,8 +549,14 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   for (int i = 0; i < count; ++i) {
     if (steps[i] == 0) continue;
     const HostInst& h = b->inst[i];
-    if (h.desc.bc != LBM_BC_PERIODIC) return LBM_ERR_INVALID_ARG;   // bounded: lbm_advance_bounded
     const bool fits = fits_resident(b, h);
+    if (h.desc.bc != LBM_BC_PERIODIC) {
+      // bounded instances advance only in a bounded call, on the resident path
+      if (!b->bnd_active) return LBM_ERR_INVALID_ARG;
+      if (!fits || (b->path != 0 && b->path != 2)) return LBM_ERR_UNSUPPORTED;
+      res[std::make_tuple(h.q, h.prec, h.D, 1)].push_back(i);
+      continue;
+    }
     if (b->path == 2 && !fits) return LBM_ERR_UNSUPPORTED;
     if (b->path == 1)
       str.push_back(i);
@@ -552,7 +567,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     else if (latency && h.n >= kSplitNodes)
       slb[std::make_tuple(h.q, h.prec, h.D, 8)].push_back(i);
     else
-      res[std::make_tuple(h.q, h.prec, h.D)].push_back(i);
+      res[std::make_tuple(h.q, h.prec, h.D, 0)].push_back(i);
   }
   // item records of this call go to slot `k`; wait until the copy issued from
   // the same slot two calls ago has been consumed
@@ -567,7 +582,10 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   constexpr int kMaxJobInstances = 16;   // instances per job (one wave each at least)
   for (const auto& group : res) {
     {
-      const int pr = std::get<1>(group.first), code = std::get<2>(group.first);
+      const int pr = std::get<1>(group.first);
+      const int bnd = std::get<3>(group.first);
+      // the kernel: the variant, and whether its jobs reset boundary layers
+      const int code = std::get<2>(group.first) | (bnd << 16);
       std::vector<int> g = group.second;
       const size_t es = pr ? sizeof(float) : sizeof(double);
       const int q = std::get<0>(group.first);
@@ -649,6 +667,8 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
         jb.count = m;
         jb.steps = (int)bn.steps;
         jb.degree = bn.variant;
+        jb.bounded = bnd;
+        jb.pad_ = 0;
         int t0 = 0, off = 0;
         for (int u = 0; u < m; ++u) {
           const int i = bn.members[u];
@@ -662,6 +682,9 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
           it.lds_off = off;
           it.t0 = t0;
           it.nt = 64 * wv[u];
+          it.phib = bnd ? b->bnd_ptr[i] : 0;
+          it.bkind = bnd ? (h.desc.bc == LBM_BC_DIRICHLET_EQ ? 1 : 2) : 0;
+          it.layers = bnd ? b->bnd_layers : 0;
           it.pad_ = 0;
           t0 += it.nt;
           off += (int)(bytes_of(i) / es);
@@ -1296,6 +1319,58 @@ lbm_status lbm_advance(lbm_problem h, int64_t steps) {
   return advance(h->b, &steps);
 }
 
+namespace {
+// Bounded instances of a batch advance `steps` (<= kMaxStepsPerLaunch) steps on
+// the resident path, their boundary layers reset in LDS after every step;
+// phib[i]: host rows [steps][2 layers] of bounded instance i.
+lbm_status advance_bounded_resident(lbm_batch_s* b, int64_t steps, const double* const* phib, int layers) {
+  const int count = (int)b->inst.size();
+  int nb = 0;
+  for (int i = 0; i < count; ++i) nb += b->inst[i].desc.bc != LBM_BC_PERIODIC;
+  const size_t rows = (size_t)steps * 2 * layers;
+  const size_t need = rows * (size_t)nb;
+  // a synchronous copy: earlier launches have read the buffer by the time it lands
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  if (need > b->bound_cap) {
+    hipFree(b->bound);
+    b->bound = nullptr;
+    b->bound_cap = 0;
+    if (hipMalloc(&b->bound, sizeof(double) * need) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+    b->bound_cap = need;
+  }
+  b->bnd_ptr.assign(count, 0);
+  for (int i = 0, k = 0; i < count; ++i) {
+    if (b->inst[i].desc.bc == LBM_BC_PERIODIC) continue;
+    double* dst = b->bound + (size_t)k++ * rows;
+    LBM_HIP(hipMemcpy(dst, phib[i], sizeof(double) * rows, hipMemcpyHostToDevice));
+    b->bnd_ptr[i] = (uint64_t)(uintptr_t)dst;
+  }
+  b->bnd_active = true;
+  b->bnd_layers = layers;
+  std::vector<int64_t> st(count, steps);
+  lbm_status s = advance_pass(b, st.data());
+  b->bnd_active = false;
+  return s;
+}
+}  // namespace
+
+lbm_status lbm_batch_advance_bounded(lbm_batch b, int64_t steps, const double* const* phib, int32_t layers) {
+  if (!b || steps < 0 || steps > kMaxStepsPerLaunch) return LBM_ERR_INVALID_ARG;
+  int hmax = 0;
+  for (const HostInst& h : b->inst)
+    if (h.desc.bc != LBM_BC_PERIODIC) hmax = std::max(hmax, h.q / 2);
+  if (layers == 0) layers = hmax;
+  if (layers < hmax || layers > 32) return LBM_ERR_INVALID_ARG;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    const HostInst& h = b->inst[i];
+    if (h.desc.bc == LBM_BC_PERIODIC) continue;
+    if (steps > 0 && (!phib || !phib[i])) return LBM_ERR_INVALID_ARG;
+    if (h.n < 2 * layers + 2) return LBM_ERR_INVALID_ARG;
+  }
+  if (steps == 0) return LBM_OK;
+  return advance_bounded_resident(b, steps, phib, layers);
+}
+
 lbm_status lbm_advance_bounded(lbm_problem h, int64_t steps, const double* phib, int32_t layers) {
   if (!h || steps < 0 || (steps > 0 && !phib)) return LBM_ERR_INVALID_ARG;
   lbm_batch_s* b = h->b;
@@ -1305,6 +1380,11 @@ lbm_status lbm_advance_bounded(lbm_problem h, int64_t steps, const double* phib,
   if (layers == 0) layers = H;
   if (layers < H || layers > 32 || in.n < 2 * layers + 2) return LBM_ERR_INVALID_ARG;
   if (steps == 0) return LBM_OK;
+  // LDS-resident unless the streaming path is asked for or the state does not fit
+  if ((b->path == 0 || b->path == 2) && fits_resident(b, in) && steps <= kMaxStepsPerLaunch) {
+    const double* rows[1] = {phib};
+    return advance_bounded_resident(b, steps, rows, layers);
+  }
   lbm_status s = ensure_second_buffer(b, in.f32);
   if (s != LBM_OK) return s;
   const size_t need = (size_t)steps * 2 * layers;

@@ -103,6 +103,7 @@ def library() -> ctypes.CDLL:
         "lbm_batch_create": (I32, [DP, I32, P, P]),
         "lbm_batch_load_phi": (I32, [P, P]),
         "lbm_batch_advance": (I32, [P, P]),
+        "lbm_batch_advance_bounded": (I32, [P, I64, P, I32]),
         "lbm_batch_read_phi": (I32, [P, I32, P, P]),
         "lbm_batch_last_advance_ms": (I32, [P, P]),
         "lbm_batch_set_path": (I32, [P, I32]),
@@ -336,6 +337,31 @@ class Batch:
         s = np.ascontiguousarray(steps, dtype=np.int64)
         assert s.size == len(self.problems)
         _check(library().lbm_batch_advance(self._h, s.ctypes.data), "lbm_batch_advance")
+
+    def advance_bounded(self, phibs, layers: int = 0):
+        """Every instance advances len(rows) steps; bounded instance i resets its
+        outer layers after step s from phibs[i][s] (left layers, then right);
+        phibs[i] is None for periodic instances."""
+        arrs, steps = [], None
+        for i, a in enumerate(phibs):
+            if a is None:
+                arrs.append(None)
+                continue
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            if a.ndim != 2 or a.shape[1] % 2:
+                raise ValueError("phib rows must be (steps, 2 * layers)")
+            if steps is not None and a.shape[0] != steps:
+                raise ValueError("every bounded instance needs the same number of rows")
+            steps = a.shape[0]
+            if layers and a.shape[1] != 2 * layers:
+                raise ValueError("phib width is not 2 * layers")
+            layers = a.shape[1] // 2
+            arrs.append(a)
+        if steps is None:
+            raise ValueError("no bounded instance")
+        ptrs = (ctypes.c_void_p * len(arrs))(*[a.ctypes.data if a is not None else None for a in arrs])
+        _check(library().lbm_batch_advance_bounded(self._h, int(steps), ctypes.cast(ptrs, ctypes.c_void_p), int(layers)),
+               "lbm_batch_advance_bounded")
 
     def read_phi(self, i: int):
         """(phi, status) of instance i; status is OK or NONFINITE for that instance."""

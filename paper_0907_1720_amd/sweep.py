@@ -24,8 +24,13 @@ def global_relative_error(phi: np.ndarray, exact: np.ndarray) -> float:
 
 
 def tau_sweep(problem: Problem, phi0: np.ndarray, steps: int, taus: Sequence[float],
-              exact: Optional[np.ndarray] = None, stream: Optional[int] = None) -> dict:
+              exact: Optional[np.ndarray] = None, stream: Optional[int] = None,
+              phib: Optional[np.ndarray] = None) -> dict:
     """Runs `problem` at every tau in `taus` for `steps` steps in one batch.
+
+    A bounded problem (bc != 0, the setting of the paper's examples) needs
+    `phib`, the exact phi at its outer layers after every step, shape
+    (steps, 2 layers) -- the same for every tau.
 
     Returns {"tau": [...], "status": [...], "phi": [...], "E": [...], "tau_opt": t}:
     taus the library rejects (tau <= 1/2, a vanishing tau_k that a term needs)
@@ -41,7 +46,12 @@ def tau_sweep(problem: Problem, phi0: np.ndarray, steps: int, taus: Sequence[flo
     b = lbm.Batch(runs, stream=stream) if runs else None
     if b is not None:
         b.load_phi([phi0] * len(runs))
-        b.advance(int(steps))
+        if problem.bc:
+            if phib is None or len(phib) != steps:
+                raise ValueError("a bounded sweep needs phib rows for every step")
+            b.advance_bounded([phib] * len(runs))
+        else:
+            b.advance(int(steps))
     k = 0
     for i, st in enumerate(out["status"]):
         if st != lbm.OK:

@@ -295,6 +295,60 @@ def config4_instance(i: int, prec: int = F64, steps: int = 5000) -> Instance:
     return Instance(p, phi0, steps, exact=ex)
 
 
+def table8_bounded(tau: float = 0.97, prec: int = F64):
+    """The bounded KdV-Burgers example of Sec. IV (Table VIII):
+    u_t + u u_x - 9e-4 u_xx + 2e-5 u_xxx = 0 on [-4, 4] with both end points,
+    dx = dt = 0.01, D1Q5, non-equilibrium extrapolation boundaries, and its
+    travelling front 2 xi (1 - 1 / (1 + exp(2 nu (x - xi t)))^2),
+    nu = -gamma / (10 delta), xi = 6 gamma^2 / (25 delta).
+    Returns (problem, x, exact(x, t))."""
+    ga, de = 9e-4, 2e-5
+    nu, xi = -ga / (10 * de), 6 * ga ** 2 / (25 * de)
+
+    def exact(x, t):
+        return 2 * xi * (1 - 1 / (1 + np.exp(2 * nu * (x - xi * t))) ** 2)
+
+    n = 801
+    x = np.linspace(-4.0, 4.0, n)
+    p = Problem(_alpha(a2=-ga, a3=de), _pis(p1=(0, 0, 0.5), p2=(0, 1), p3=(0, 1)), n, 0.01, 0.01, tau,
+                q=5, prec=prec, x0=-4.0, name="kdv_burgers_table8", bc=2)
+    return p, x, exact
+
+
+def power_batch_instance(i: int, prec: int = F64, steps: int = 2000) -> Instance:
+    """Real-power batch: phi_t + phi^n phi_x + delta phi_xxx = 0, n = 0.5 or 1.5
+    (Bernoulli 1/2), delta ~ U[0.5, 2], N log-uniform [256, 4096] on [-20, 20),
+    dt = 0.05 dx^3 / delta, tau = 2; a Gaussian bump of height ~ U[0.1, 0.4] on
+    the background 1 (phi stays positive)."""
+    g = rng(7, i)
+    power = 0.5 if g.random() < 0.5 else 1.5
+    delta = float(g.uniform(0.5, 2.0))
+    n = int(round(math.exp(g.uniform(math.log(256), math.log(4096)))))
+    dx = 40.0 / n
+    p = power_kdv(power, delta, n, dx, 0.05 * dx ** 3 / delta, 2.0, -20.0, prec=prec)
+    x = p.grid()
+    xc, h = float(g.uniform(-15.0, 15.0)), float(g.uniform(0.1, 0.4))
+    phi0 = 1.0 + h * np.exp(-((x - xc) / 2.0) ** 2)
+    return Instance(p, np.ascontiguousarray(phi0), steps)
+
+
+def even_lattice_instance(i: int, q: int, prec: int = F64, steps: int = 2000) -> Instance:
+    """Batch on the lattices without rest velocity: D1Q4 KdV-Burgers (nu = 3,
+    delta = 0.1) or D1Q6 phi_t + phi phi_x - 3 phi_xx + 1e-3 phi_xxx +
+    0.0625 phi_xxxx - 1e-3 phi_xxxxx = 0, dx = 0.1, dt = 0.01, tau = 2 (the
+    diffusion keeps the checkerboard mode damped); N log-uniform [256, 4096];
+    a smooth random periodic state."""
+    g = rng(8 + q, i)
+    n = int(round(math.exp(g.uniform(math.log(256), math.log(4096)))))
+    if q == 4:
+        p = kdv_burgers(3.0, 0.1, n, 0.1, 0.01, 2.0, 0.0, q=4, prec=prec)
+    else:
+        p = dissipative_fifth_order(3.0, 1e-3, 0.0625, -1e-3, n, 0.1, 0.01, 2.0, 0.0, q=6, prec=prec)
+    x = np.arange(n) / n
+    phi0 = 0.5 + 0.3 * np.sin(2 * np.pi * x + float(g.uniform(0, 6))) + 0.1 * np.cos(6 * np.pi * x)
+    return Instance(p, phi0, steps)
+
+
 def random_m6_problem(g: np.random.Generator, n: int) -> Problem:
     """Random sixth-order equation: alpha_k ~ U[-1, 1] with alpha_6 := -|alpha_6| (a
     dissipative top order), Pi_k random cubics without constant term, dx = 0.1,

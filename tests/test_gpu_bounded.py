@@ -134,3 +134,116 @@ def test_bounded_calls_are_checked():
         per.advance_bounded(np.zeros((4, 6)))
     assert e.value.status == lbm.INVALID_ARG
     per.close()
+
+
+# ---------------------------------------------------------------------------
+# bounded problems on the LDS-resident path (layers reset in LDS every step)
+# ---------------------------------------------------------------------------
+
+def _bounded_run(key, steps, path, prec=W.F64, tau=None):
+    t, p, x, ex, kind = _table_problem(key)
+    p = dataclasses.replace(p, bc=KIND[kind], prec=prec, tau=tau if tau is not None else p.tau)
+    layers = p.lattice() // 2
+    s = lbm.Solver(p)
+    s.set_path(path)
+    s.load_phi(ex(x, 0.0))
+    s.advance_bounded(_boundary_values(x, ex, p.dt, 0, steps, layers))
+    out = s.read_phi()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", [W.F64, W.F32_DEV])
+@pytest.mark.parametrize("key", ["table_VIII_s1", "table_VI_s1_c10", "table_I_c10", "table_IV_q7_c10"])
+def test_bounded_resident_bitwise_equals_streaming(key, prec):
+    for steps in (1, 2, 77):
+        say("case bounded resident", key, prec, steps)
+        a = _bounded_run(key, steps, lbm.PATH_STREAM, prec)
+        b = _bounded_run(key, steps, lbm.PATH_RESIDENT, prec)
+        assert np.array_equal(a, b), steps
+
+
+def test_bounded_batch_with_forced_chunks_and_periodic_neighbours():
+    """Several bounded instances and periodic ones in one batch, the steps split
+    into chunks (each chunk reads its own boundary rows): every result equals
+    its own single solve."""
+    steps = 150
+    probs, phis, rows, single = [], [], [], []
+    for key in ("table_VIII_s1", "table_VI_s1_c10", "table_I_c10"):
+        t, p, x, ex, kind = _table_problem(key)
+        p = dataclasses.replace(p, bc=KIND[kind])
+        probs.append(p)
+        phis.append(ex(x, 0.0))
+        rows.append(_boundary_values(x, ex, p.dt, 0, steps, 3))
+        single.append((key, p))
+    for n in (300, 1000):
+        probs.append(W.kdv(0.5, n, 0.1, 1e-4, 2.0, 0.0))
+        phis.append(0.4 + 0.3 * np.sin(2 * np.pi * np.arange(n) / n))
+        rows.append(None)
+    for chunks in (0, 7):
+        b = lbm.Batch(probs)
+        b.set_resident(0, chunks)
+        b.load_phi(phis)
+        b.advance_bounded(rows, 3)
+        got = [b.read_phi(i) for i in range(len(probs))]
+        b.close()
+        for i, (p, phi0) in enumerate(zip(probs, phis)):
+            g, st = got[i]
+            assert st == lbm.OK
+            s = lbm.Solver(p)
+            s.set_path(lbm.PATH_STREAM)
+            s.load_phi(phi0)
+            if rows[i] is None:
+                s.advance(steps)
+            else:
+                s.advance_bounded(rows[i], 3)
+            ref = s.read_phi()
+            s.close()
+            say("case bounded batch", chunks, i)
+            assert np.array_equal(g, ref), (chunks, i)
+
+
+def test_bounded_tau_sweep_in_one_batch():
+    """The paper's tau_opt search for Table VIII as one batch of bounded runs."""
+    from paper_0907_1720_amd import sweep
+    t, p, x, ex, kind = _table_problem("table_VIII_s1")
+    p = dataclasses.replace(p, bc=KIND[kind])
+    steps = 1000                                          # t = 10, the table's first time
+    taus = [0.6, 0.8, 0.9, 0.97, 1.05, 1.2, 1.5, 2.0]
+    phib = _boundary_values(x, ex, p.dt, 0, steps, 2)
+    out = sweep.tau_sweep(p, ex(x, 0.0), steps, taus, exact=ex(x, steps * p.dt), phib=phib)
+    for tau, st, phi in zip(taus, out["status"], out["phi"]):
+        if tau < 0.97:                                    # unstable: the oracle blows up too
+            assert st == lbm.NONFINITE, tau
+            continue
+        assert st == lbm.OK, tau
+        ref = _bounded_run("table_VIII_s1", steps, lbm.PATH_STREAM, tau=tau)
+        assert np.array_equal(phi, ref), tau
+    # the oracle at two of the taus
+    for k in (3, 6):
+        want = O.run_bounded(dataclasses.replace(p, bc=0, tau=taus[k]), x, ex, steps, kind, report=[steps])[steps]
+        assert rel2(out["phi"][k], want) <= 1e-12
+    say("  tau sweep E", [f"{e:.3g}" for e in out["E"]], "tau_opt", out["tau_opt"])
+    assert out["tau_opt"] == 0.97                         # the paper's choice: the stable edge
+    # the paper's printed E at t = 10 for its tau
+    assert abs(out["E"][3] - t["E"][0]) <= 1e-2 * t["E"][0]
+
+
+def test_bounded_batch_calls_are_checked():
+    t, p, x, ex, kind = _table_problem("table_VIII_s1")
+    pb = dataclasses.replace(p, bc=KIND[kind])
+    big = dataclasses.replace(pb, n=20001, x0=-100.0)     # FP64 D1Q5: 800 KB, beyond one LDS
+    b = lbm.Batch([pb, big])
+    b.load_phi([ex(x, 0.0), np.ones(20001)])
+    with pytest.raises(lbm.LBMError) as e:
+        b.advance_bounded([np.zeros((4, 4)), np.zeros((4, 4))])
+    assert e.value.status == lbm.UNSUPPORTED
+    with pytest.raises(lbm.LBMError) as e:
+        b.advance(4)                                      # bounded instances need boundary rows
+    assert e.value.status == lbm.INVALID_ARG
+    b.close()
+    s = lbm.Solver(big)                                   # a single problem falls back to streaming
+    s.load_phi(np.ones(20001))
+    s.advance_bounded(np.ones((3, 4)))
+    assert np.allclose(s.read_phi(), 1.0, atol=1e-12)
+    s.close()

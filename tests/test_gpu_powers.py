@@ -2,9 +2,11 @@
 with a real exponent n in beta u^n u_x and real p, q in alpha_2 (u^p)_xx,
 alpha_3 (u^q)_xxx) against the CPU oracle.
 
-The kernels evaluate phi^nu = exp2(nu log2 phi) in FP64 (phi >= 0) for each
-distinct fractional part nu of the exponents; the oracle takes numpy powers of
-the exact binary exponents.  Both are correctly rounded to about an ulp, so the
+The kernels evaluate phi^nu in FP64 (phi >= 0) for each distinct fractional
+part nu of the exponents -- square roots when every nu is 1/2, 1/4 or 3/4 (the
+n = 0.5, 1.5 cases below), exp2(nu log2 phi) otherwise (the n = 1/3 case); the
+oracle takes numpy powers of the exact binary exponents.  Both are accurate to
+about an ulp, so the
 FP64 bar stays relative L2 <= 1e-12; every kernel path evaluates the same
 per-node function and must agree bitwise with the HBM streaming step.  FP32
 deviation storage: 1e-4 (as for the polynomial equilibria).
