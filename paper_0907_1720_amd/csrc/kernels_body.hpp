@@ -284,11 +284,14 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
   const bool act = mine >= 0;
   T* S = L + ji.lds_off;
   T* g = reinterpret_cast<T*>(ji.addr);
-  const int t = tid - ji.t0, nt = ji.nt, n = ji.n;
+  // threads beyond the job's instances hold a zeroed record (nt = 0): they get
+  // a nonzero stride so that nothing below divides by zero (undefined
+  // behaviour, which the compiler may use to assume every thread is active)
+  const int t = tid - ji.t0, nt = act ? ji.nt : 64, n = act ? ji.n : 0;
   const DevCoef* cf = coefs + (act ? ji.inst : 0);
   const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
   // interior odd sweeps give threads r..nt-1 one node less, r = (n - 2H) mod nt
-  const int r = (n - 2 * H) % nt;
+  const int r = act ? (n - 2 * H) % nt : 0;
   const int seam0 = (r > 0 && r + 2 * H <= nt) ? r : 0;
   if (act)
     for (int j = 0; j < Q; ++j)

@@ -606,7 +606,10 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int cu_waves = 4 * std::max(1, std::min(8, 512 / vgprs));
       const int jobs_per_cu = std::max<int>(1, (int)(b->lim.lds_max / cap));
       const int kJobWaves = std::max(1, std::min(16, cu_waves / jobs_per_cu));
-      const int kJobInstances = std::min(kMaxJobInstances, kJobWaves);
+      // a pass that leaves most CUs idle (latency regime) gives every instance a
+      // job of its own and up to a wave per 64 nodes: its steps end sooner
+      const int kJobInstances = latency ? 1 : std::min(kMaxJobInstances, kJobWaves);
+      const int kNodesPerWave = latency ? 64 : 128;
       struct Bin { int64_t steps; int variant; size_t bytes; std::vector<int> members; };
       std::vector<Bin> bins;
       size_t open_from = 0;   // bins before this index have another step count or variant
@@ -629,7 +632,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       std::vector<Planned> plan;
       for (const Bin& bn : bins) {
         // waves: one each, then one more at a time to the member with the most
-        // nodes per wave (at most one wave per 128 nodes)
+        // nodes per wave (at most one wave per kNodesPerWave nodes)
         const int m = (int)bn.members.size();
         std::vector<int> wv(m, 1);
         int total = m;
@@ -638,7 +641,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
           double load = 0.0;
           for (int u = 0; u < m; ++u) {
             const int n = b->inst[bn.members[u]].n;
-            if (wv[u] >= (n + 127) / 128) continue;
+            if (wv[u] >= (n + kNodesPerWave - 1) / kNodesPerWave) continue;
             const double l = (double)n / wv[u];
             if (l > load) {
               load = l;

@@ -197,3 +197,22 @@ def test_power_sums_bounded_matches_oracle(kind):
     err = rel2(got, want)
     say("case powers bounded", kind, f"{err:.2e}")
     assert err <= FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["power_kdv_1.5", "family_a_third_q6"])
+def test_small_and_large_instance_in_one_launch(name):
+    """A 64-node and a 700-node instance of one variant: in a small batch each
+    gets a workgroup of its own, and the small one's workgroup carries threads
+    beyond its instance (regression: those threads once divided by zero)."""
+    probs, phis = [], []
+    for k, n in enumerate([64, 700]):
+        p, _ = case(name, n)
+        probs.append(p)
+        phis.append(_phi(n, 3 + k))
+    b = lbm.Batch(probs)
+    b.load_phi(phis)
+    b.advance(60)
+    got = [b.read_phi(i)[0] for i in range(2)]
+    b.close()
+    for g, p, phi0 in zip(got, probs, phis):
+        assert np.array_equal(g, _run(p, phi0, 60, lbm.PATH_STREAM)), p.n
