@@ -92,6 +92,17 @@ def algorithmic_flops_per_nu(G: np.ndarray) -> int:
     return (q - 1) + q * (2 * D + 2)
 
 
+def algorithmic_flops_power_sum(nu: np.ndarray, G: np.ndarray) -> int:
+    """Arithmetic of one node update for an equilibrium with real powers,
+    f_eq_j = sum_c phi^nu_c sum_d G[c, j, d] phi^d (G: F x q x (D+1)): the phi
+    sum (q - 1 adds), per population a Horner over each class's degree, one FMA
+    per further class, the BGK FMA.  The powers phi^nu (square roots, or
+    exp2/log2) are not counted."""
+    F, q = G.shape[0], G.shape[1]
+    deg = [max((d for d in range(G.shape[2]) if np.any(G[c, :, d])), default=0) for c in range(F)]
+    return (q - 1) + q * (sum(2 * d for d in deg) + 2 * (F - 1) + 2)
+
+
 def _oracle_one(args):
     i, steps = args
     from oracle import lbm_oracle as O
@@ -252,11 +263,12 @@ def main():
         nu = sum(x.problem.n for x in insts) * steps
         out = {"workload": label, "instances": len(insts), "steps": steps, "node_updates": nu,
                "kernel_ms": ms, "node_updates_per_s": nu / (ms * 1e-3), "status_ok": ok}
-        try:
-            fl = sum(x.problem.n * steps * algorithmic_flops_per_nu(lbm.coefficients(x.problem)) for x in insts)
-            out["alu_frac"] = fl / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS
-        except lbm.LBMError:   # real powers: no polynomial table (flops of exp2/log2 are not counted)
-            pass
+        fl = 0
+        for x in insts:
+            nu, G = lbm.coefficients_general(x.problem)
+            f = algorithmic_flops_per_nu(G[0]) if len(nu) == 1 else algorithmic_flops_power_sum(nu, G)
+            fl += x.problem.n * steps * f
+        out["alu_frac"] = fl / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS
         return out
 
     def next_rows():

@@ -276,9 +276,11 @@ typedef struct {
    launch, workgroups per CU), the resident step chunking and, for at most 16
    instances, HBM streaming instead of LDS residency -- on a copy of the batch
    advanced probe_steps per candidate (best of two passes after a warm-up),
-   and applies the fastest to b (a candidate must beat the best so far by 3%).  The state of b is not changed.  Needs device
-   memory for a second copy of the batch (OUT_OF_MEMORY otherwise); synchronises
-   b's stream; UNSUPPORTED for the batch behind a server.  out may be NULL. */
+   and applies the fastest to b (a candidate must beat the best so far by 3%).
+   The state of b is not changed.  Needs device memory for a second copy of the
+   batch (OUT_OF_MEMORY otherwise); synchronises b's stream; UNSUPPORTED for the
+   batch behind a server; INVALID_ARG for a batch with bounded instances (they
+   advance only with their boundary rows).  out may be NULL. */
 lbm_status lbm_batch_autotune(lbm_batch b, int64_t probe_steps, lbm_tuning* out);
 
 lbm_status lbm_batch_destroy(lbm_batch b);

@@ -257,6 +257,41 @@ def test_config2_batch_matches_oracle(prec, tol, cons):
     b.close()
 
 
+# sum(phi) drift over all 4096 instances: FP32 storage rounds every stored
+# deviation each step (relative 2^-24 of populations that can exceed phi by an
+# order of magnitude), a random walk of ~2^-24 sqrt(steps) |g| / |phi| -- the worst
+# instance measured 3.7e-5
+@pytest.mark.parametrize("prec,tol,cons", [(W.F64, FP64_TOL, 1e-12), (W.F32_DEV, FP32_TOL, 1e-4)])
+def test_config2_full_size_as_benchmarked(prec, tol, cons):
+    """The whole 4096-instance batch, 5000 steps, in the launch configuration the
+    benchmark times (automatic planner): six instances checked against the oracle
+    (smallest, largest, the first KdV and mKdV, two more), sum(phi) conserved by
+    every instance."""
+    insts = [W.config2_instance(i, prec=prec) for i in range(4096)]
+    steps = insts[0].steps
+    say("case config2 full", prec, len(insts), steps)
+    b = lbm.Batch([i.problem for i in insts])
+    b.load_phi([i.phi0 for i in insts])
+    b.advance(steps)
+    ns = np.array([i.problem.n for i in insts])
+    names = [i.problem.name for i in insts]
+    sample = sorted({int(np.argmin(ns)), int(np.argmax(ns)), names.index("kdv"), names.index("mkdv"), 1234, 4095})
+    worst = 0.0
+    for k in range(len(insts)):
+        got, st = b.read_phi(k)
+        assert st == lbm.OK, k
+        drift = abs(got.sum() - insts[k].phi0.sum()) / np.abs(insts[k].phi0).sum()
+        worst = max(worst, drift)
+        if k in sample:
+            want = O.run(dataclasses.replace(insts[k].problem, prec=W.F64), insts[k].phi0, steps)
+            err = rel2(got, want)
+            say("  inst", k, names[k], ns[k], f"{err:.2e}")
+            assert err <= tol, (k, err)
+    b.close()
+    say("  worst sum drift", f"{worst:.2e}")
+    assert worst <= cons
+
+
 def test_batch_instance_alone_equals_in_mix():
     insts = _config2(W.F64, 12)
     b = lbm.Batch([i.problem for i in insts])
@@ -420,6 +455,34 @@ def test_config4_sample(i):
     p32 = dataclasses.replace(inst.problem, prec=W.F32_DEV)
     got32 = gpu_run(p32, inst.phi0, steps)
     assert rel2(got32, want) <= FP32_TOL
+
+
+@pytest.mark.parametrize("which", ["ks8192", "kawahara_k22"])
+def test_large_grid_batches_as_benchmarked(which):
+    """The large-grid batches exactly as the benchmark times them (slabs over
+    co-resident workgroups, automatic planner): two instances checked against
+    the oracle, every instance finite."""
+    if which == "ks8192":
+        insts, steps = [W.config3_instance(8192, i) for i in range(256)], 640
+        sample = [0, 255]
+    else:
+        insts, steps = [W.config4_instance(i) for i in range(512)], 500
+        ns = [i.problem.n for i in insts]
+        sample = [ns.index(max(ns)), next(k for k, x in enumerate(insts) if x.problem.name != insts[0].problem.name)]
+    say("case large batch", which, len(insts), steps)
+    b = lbm.Batch([i.problem for i in insts])
+    b.load_phi([i.phi0 for i in insts])
+    b.advance(16)
+    b.advance(steps)
+    for k in range(len(insts)):
+        got, st = b.read_phi(k)
+        assert st == lbm.OK, k
+        if k in sample:
+            want = O.run(insts[k].problem, insts[k].phi0, steps + 16)
+            err = rel2(got, want)
+            say("  inst", k, insts[k].problem.name, insts[k].problem.n, f"{err:.2e}")
+            assert err <= FP64_TOL, (k, err)
+    b.close()
 
 
 def test_random_sixth_order_equation():
