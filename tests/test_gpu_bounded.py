@@ -65,11 +65,14 @@ def gpu_bounded(key, reports, prec=W.F64, am=0):
 # ~5% per step (a 1e-15 relative change of phi0 moves the oracle's own result
 # by 7e-15, 1.1e-13 and 6.3e-12 after 66, 120 and 200 steps; Table IV: 6.5e-13
 # after 200; Table I at c = 10: 2.1e-14, 6.0e-14, 5.8e-10 after 66, 80, 200),
-# so those are compared where that sensitivity is <= 1e-13.
+# so those are compared where that sensitivity is <= 1e-13 (Table VII at c = 10:
+# 2.5e-15 after 67 steps, 2.4e-13 after 200, so 150).
 @pytest.mark.parametrize("key,steps", [("table_VI_s1_c10", 200), ("table_VI_s2_c10", 200),
                                        ("table_V_s1_c10", 120), ("table_IV_q7_c10", 100),
                                        ("table_I_c10", 80), ("table_I_c100", 600),
-                                       ("table_VIII_s1", 500)])
+                                       ("table_VIII_s1", 500), ("table_II_c10", 1200),
+                                       ("table_VII_s1_c10", 150), ("table_VII_s2_c10", 150),
+                                       ("table_VII_s1_c100", 2000)])
 def test_bounded_matches_oracle(key, steps):
     reports = [steps // 3, steps]
     say("case bounded", key, steps)
@@ -84,7 +87,9 @@ def test_bounded_matches_oracle(key, steps):
 # tolerances on the paper's printed errors: those of the oracle's own table pins
 @pytest.mark.parametrize("key,rtol", [("table_VI_s1_c10", 5e-4), ("table_VI_s2_c10", 5e-4),
                                       ("table_V_s1_c10", 5e-4), ("table_I_c10", 3e-2),
-                                      ("table_I_c100", 3e-2), ("table_VIII_s1", 1e-2)])
+                                      ("table_I_c100", 3e-2), ("table_VIII_s1", 1e-2),
+                                      ("table_II_c10", 2e-2), ("table_VII_s1_c10", 1e-2),
+                                      ("table_VII_s2_c10", 1e-2), ("table_VII_s1_c100", 1e-2)])
 def test_bounded_reproduces_paper_tables(key, rtol):
     t, *_ = _table_problem(key)
     reports = [int(round(tt / t["dt"])) for tt in t["times"]]

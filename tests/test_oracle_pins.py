@@ -501,6 +501,16 @@ def _table_problem(key):
         ex = lambda x, tt: 2 * xi * (1 - 1 / (1 + np.exp(2 * nu * (x - xi * tt))) ** 2)
         p = W.Problem(W._alpha(a2=-ga, a3=de), W._pis(p1=(0, 0, 0.5), p2=(0, 1), p3=(0, 1)), **kw)
         kind = "nee"
+    elif key.startswith("table_VII"):
+        ex = lambda x, tt: (105 / 169) / np.cosh((x - 205 * tt / 169 - 20.0) / (2 * math.sqrt(13))) ** 4
+        p = W.Problem(W._alpha(a3=1.0, a5=-1.0), W._pis(p1=(0, 1, 0.5), p3=(0, 1), p5=(0, 1)), **kw)
+        kind = "eq"
+    elif key.startswith("table_II_"):
+        b2, k2, x02 = 5.0, 1 / (2 * math.sqrt(19)), -25.0
+        ex = lambda x, tt: b2 + 15 / (19 * math.sqrt(19)) * (-3 * np.tanh(k2 * (x - b2 * tt - x02))
+                                                             + np.tanh(k2 * (x - b2 * tt - x02)) ** 3)
+        p = W.Problem(W._alpha(a2=-1.0, a4=1.0), W._pis(p1=(0, 0, 0.5), p2=(0, 1), p4=(0, 1)), **kw)
+        kind = "nee"
     elif key.startswith("table_I_"):
         b, k, x0 = 5.0, 0.5 * math.sqrt(11 / 19), -12.0
         ex = lambda x, tt: b + (15 / 19) * math.sqrt(11 / 19) * (-9 * np.tanh(k * (x - b * tt - x0))
@@ -540,6 +550,20 @@ def test_paper_table_viii_kdv_burgers():
     got, want = _table_errors("table_VIII_s1")
     for g, w in zip(got, want):
         assert abs(g - w) <= 1e-2 * w, (got, want)
+
+
+@pytest.mark.parametrize("key", ["table_VII_s1_c10", "table_VII_s2_c10", "table_VII_s1_c100"])
+def test_paper_table_vii_kdv_kawahara(key):
+    """Both schemes; the D1Q7 flux Pi_1 = u + u^2/2 carries a linear term."""
+    got, want = _table_errors(key)
+    for g, w in zip(got, want):
+        assert abs(g - w) <= 1e-2 * w, (got, want)
+
+
+def test_paper_table_ii_kuramoto_sivashinsky():
+    got, want = _table_errors("table_II_c10")
+    for g, w in zip(got, want):
+        assert abs(g - w) <= 2e-2 * w, (got, want)
 
 
 @pytest.mark.parametrize("key", ["table_I_c10", "table_I_c100"])
