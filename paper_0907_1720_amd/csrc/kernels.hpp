@@ -1,4 +1,6 @@
-// Launchers of the HIP kernels (kernels.hip).  All take device pointers.
+// Launchers of the HIP kernels (defined in kernels.hip; the kernels are in
+// kernels_body.hpp, one instantiation per lattice size in kernels_q.hip).  All
+// take device pointers.
 #pragma once
 
 #include "device.hpp"

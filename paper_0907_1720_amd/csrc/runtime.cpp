@@ -1,6 +1,8 @@
 // C-ABI runtime: problem and batch handles, device memory, the planner that
-// chooses between the on-chip resident and the HBM streaming kernels, and the
-// read-outs.  Host code only; kernels live in kernels.hip.
+// chooses between the LDS-resident, slab, temporal-blocking and HBM streaming
+// kernels, bounded advances, the server, the autotuner and the read-outs.
+// Host code only; the kernels live in kernels_body.hpp (instantiated per
+// lattice by kernels_q.hip) and their launchers in kernels.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
