@@ -201,3 +201,13 @@ def test_power_sum_validation():
     as_int = W.family_b(0.5, 0.75, 2.0, -0.25, 1.0, 0.5, 2.0, 64, 0.25, 0.015625, 1.25, 0.0, q=5)
     nu, G = lbm.coefficients_general(as_int)
     assert list(nu) == [0.0]
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No CPU fallback: without the built HIP library every entry point raises."""
+    monkeypatch.setattr(lbm, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(lbm, "_lib", None)
+    with pytest.raises(ImportError):
+        lbm.library()
+    with pytest.raises(ImportError):
+        lbm.validate(PROBLEMS["kdv"])
