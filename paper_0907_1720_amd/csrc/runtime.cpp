@@ -718,6 +718,8 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   size_t xbuf_need = 0;
   int flags_need = 0;
   int min_per_cu = 1 << 30;
+  const int tin_slab0 = tin_used;
+  std::vector<int> slab_insts;
   for (const auto& group : slb) {
     {
       const int qq = std::get<0>(group.first), pr = std::get<1>(group.first), code = std::get<2>(group.first);
@@ -770,6 +772,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
         }
         L.count += ks;
         ++tin_used;
+        slab_insts.push_back(i);
       }
       if (L.count) slaunch.push_back(L);
     }
@@ -785,7 +788,20 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   // otherwise one after another (each launch alone fits by construction)
   int total_slabs = 0;
   for (const SlabLaunch& S : slaunch) total_slabs += S.count;
-  const bool slab_side_by_side = slaunch.size() > 1 && 2 * (int64_t)total_slabs <= (int64_t)min_per_cu * b->lim.cus;
+  bool slab_side_by_side = slaunch.size() > 1 && 2 * (int64_t)total_slabs <= (int64_t)min_per_cu * b->lim.cus;
+  // A small pass (a serving round) whose slab launches would run one after
+  // another is bound by that sequence of mostly idle launches; temporal
+  // blocking has no co-residency condition, so its groups run side by side:
+  // those instances take it instead (results are the same bit for bit)
+  if (latency && slaunch.size() > 1 && !slab_side_by_side) {
+    for (int i : slab_insts) til[b->inst[i].q][b->inst[i].prec].push_back(i);
+    tin_used = tin_slab0;
+    svec.clear();
+    slaunch.clear();
+    xbuf_need = 0;
+    flags_need = 0;
+    slab_side_by_side = false;
+  }
   if (!svec.empty()) {
     if ((int)svec.size() > b->slabs_cap || xbuf_need > b->xbuf_bytes || flags_need > b->sflags_cap) {
       // grow the slab tables and exchange buffers; earlier passes must be done with them
@@ -1785,9 +1801,15 @@ lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int3
   }
   sv->queue.erase(sv->queue.begin(), sv->queue.begin() + qi);
   // one block.  A round lasts as long as its slowest request's block; requests
-  // whose steps cost less (lattice size x polynomial degree) take
-  // proportionally more steps in the same round, up to 8 blocks
-  auto step_cost = [&](size_t k) { return (double)b->inst[k].q * ((b->inst[k].D & 0xff) + 3); };
+  // whose steps take less time take proportionally more steps in the same
+  // round, up to 8 blocks.  A step's time is estimated as its arithmetic per
+  // node (lattice size x polynomial degree) times the node sweeps of one
+  // workgroup (1024 threads; larger grids are spread over several)
+  auto step_cost = [&](size_t k) {
+    const HostInst& h = b->inst[k];
+    const int sweeps = (std::min(h.n, 4096) + 1023) / 1024;
+    return (double)h.q * ((h.D & 0xff) + 3) * sweeps;
+  };
   double cmax = 0.0;
   for (size_t k = 0; k < sv->slots.size(); ++k)
     if (sv->slots[k].active) cmax = std::max(cmax, step_cost(k));
