@@ -146,6 +146,8 @@ def main():
                     help="time only the large-grid workloads (for profiler runs); prints a reduced line")
     ap.add_argument("--next-only", action="store_true",
                     help="time only the extension workloads (bounded sweep, real powers, D1Q4/D1Q6)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving measurement (Poisson request stream)")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the FP32 batch (for profiler runs); prints a reduced line")
     args = ap.parse_args()
@@ -322,6 +324,24 @@ def main():
                                   "1024 D1Q6 fifth-order dissipative equations, N log-uniform [256, 4096], FP64")
         return out
 
+    def serve():
+        # Poisson arrivals of the mixed request stream (7 equation families,
+        # N log-uniform [128, 16384], steps log-uniform [1e3, 1e5], FP32/FP64)
+        from paper_0907_1720_amd import serving
+        reqs = [W.serving_request(i) for i in range(args.serve_requests)]
+        srv = lbm.Server(args.serve_budget_gb << 30, max_slots=1024, max_n=16384, block_steps=args.serve_block,
+                         stream=stream.cuda_stream)
+        r = serving.run_poisson(srv, reqs, rate=args.serve_rate, seed=1)
+        srv.close()
+        return {"requests": r["requests"], "arrival_rate_per_s": r["rate_per_s"],
+                "p50_latency_s": r["p50_latency_s"], "p99_latency_s": r["p99_latency_s"],
+                "node_updates_per_s": r["node_updates_per_s"], "wall_s": r["wall_s"],
+                "nonfinite": r["nonfinite"], "block_steps": args.serve_block,
+                "budget_bytes": args.serve_budget_gb << 30}
+
+    if args.serving_only:
+        print(json.dumps({"metric": "serving latency only", "serving": serve()}))
+        return
     if args.next_only:
         print(json.dumps({"metric": "extensions (next rows) only", "next_rows": next_rows()}))
         return
@@ -360,14 +380,7 @@ def main():
         s.close()
     plain = nu / secs
 
-    # serving: Poisson arrivals of the mixed request stream (7 equation families,
-    # N log-uniform [128, 16384], steps log-uniform [1e3, 1e5], FP32/FP64)
-    from paper_0907_1720_amd import serving
-    reqs = [W.serving_request(i) for i in range(args.serve_requests)]
-    srv = lbm.Server(args.serve_budget_gb << 30, max_slots=1024, max_n=16384, block_steps=args.serve_block,
-                     stream=stream.cuda_stream)
-    srv_out = serving.run_poisson(srv, reqs, rate=args.serve_rate, seed=1)
-    srv.close()
+    srv_out = serve()
 
     k_ms = float(np.mean(r32["kernel_ms"]))
     # the HBM record was taken with the planner's automatic settings
@@ -413,11 +426,7 @@ def main():
         "next_rows": nx,
         "status_ok": bool(r32["status_ok"] and r64["status_ok"]),
         "roofline": roofline,
-        "serving": {"requests": srv_out["requests"], "arrival_rate_per_s": srv_out["rate_per_s"],
-                    "p50_latency_s": srv_out["p50_latency_s"], "p99_latency_s": srv_out["p99_latency_s"],
-                    "node_updates_per_s": srv_out["node_updates_per_s"], "wall_s": srv_out["wall_s"],
-                    "nonfinite": srv_out["nonfinite"], "block_steps": args.serve_block,
-                    "budget_bytes": args.serve_budget_gb << 30},
+        "serving": srv_out,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

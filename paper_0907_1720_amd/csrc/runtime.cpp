@@ -712,7 +712,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   // (every workgroup of a launch resident at once), run one after another on
   // one lane; an instance whose slabs exceed one launch, or whose slabs would
   // be narrower than a halo, goes to temporal blocking instead
-  struct SlabLaunch { int q; int prec; int code; int first, count, s, halo, block; size_t lds; size_t xoff; int foff; };
+  struct SlabLaunch { int q; int prec; int code; int first, count, cap, s, halo, block; size_t lds; size_t xoff; int foff; };
   std::vector<SlabLaunch> slaunch;
   std::vector<DevSlab> svec;
   size_t xbuf_need = 0;
@@ -738,7 +738,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       if (cmax < halo || slab_occupancy(q, pr, code, block, lds, &per_cu) != hipSuccess) per_cu = 0;
       const int capacity = std::min(per_cu * b->lim.cus, kMaxSlabs);
       if (per_cu > 0) min_per_cu = std::min(min_per_cu, per_cu);
-      SlabLaunch L{q, pr, code, (int)svec.size(), 0, sp, halo, block, lds, 0, 0};
+      SlabLaunch L{q, pr, code, (int)svec.size(), 0, capacity, sp, halo, block, lds, 0, 0};
       for (int i : g) {
         const HostInst& h = b->inst[i];
         const int ks = cmax > 0 ? (h.n + cmax - 1) / cmax : 0;
@@ -786,14 +786,18 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   }
   // side by side only while all their workgroups fit the GPU twice over;
   // otherwise one after another (each launch alone fits by construction)
-  int total_slabs = 0;
-  for (const SlabLaunch& S : slaunch) total_slabs += S.count;
-  bool slab_side_by_side = slaunch.size() > 1 && 2 * (int64_t)total_slabs <= (int64_t)min_per_cu * b->lim.cus;
+  int64_t total_slabs = 0, total_cap = 0;
+  for (const SlabLaunch& S : slaunch) {
+    total_slabs += S.count;
+    total_cap += S.cap;
+  }
+  bool slab_side_by_side = slaunch.size() > 1 && 2 * total_slabs <= (int64_t)min_per_cu * b->lim.cus;
   // A small pass (a serving round) whose slab launches would run one after
-  // another is bound by that sequence of mostly idle launches; temporal
-  // blocking has no co-residency condition, so its groups run side by side:
-  // those instances take it instead (results are the same bit for bit)
-  if (latency && slaunch.size() > 1 && !slab_side_by_side) {
+  // another, each less than half full on average, is bound by that sequence of
+  // mostly idle launches; temporal blocking has no co-residency condition, so
+  // its groups run side by side: those instances take it instead (results are
+  // the same bit for bit).  Launches that fill the GPU keep their slabs.
+  if (latency && slaunch.size() > 1 && !slab_side_by_side && 2 * total_slabs < total_cap) {
     for (int i : slab_insts) til[b->inst[i].q][b->inst[i].prec].push_back(i);
     tin_used = tin_slab0;
     svec.clear();
