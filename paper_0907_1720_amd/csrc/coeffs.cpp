@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <vector>
 
 namespace lbm {
@@ -314,6 +315,26 @@ lbm_status collapse_general(const GPoly Pbar[kMaxQ], const qf inv[kMaxQ][kMaxQ],
     }
   }
   mdl->D = D;
+  for (int c = 0; c < mdl->gF; ++c) {
+    // lowest nonzero degree and the gcd of the gaps above it (e.g. phi^(3/2)
+    // fluxes give degrees 1, 4, 7 in the integer class: a polynomial in phi^3)
+    int lo = -1, hi = 0, step = 0;
+    for (int dg = 0; dg <= kGDeg; ++dg) {
+      bool nz = false;
+      for (int j = 0; j < q; ++j) nz = nz || mdl->gGq[c][j][dg] != 0;
+      if (!nz) continue;
+      if (lo < 0)
+        lo = dg;
+      else
+        step = std::gcd(step, dg - lo);
+      hi = dg;
+    }
+    if (lo < 0) lo = hi = 0;
+    if (step == 0) step = 1;
+    mdl->gd0[c] = lo;
+    mdl->gstep[c] = step;
+    mdl->gK[c] = (hi - lo) / step + 1;
+  }
   for (int c = 0; c < mdl->gF; ++c)
     for (int j = 0; j < q; ++j)
       for (int dg = 0; dg <= kGDeg; ++dg) {

@@ -47,6 +47,11 @@ struct Model {
   double gwG[kGClasses][kMaxQ][kGDeg + 1] = {};   // omega * gG
   __float128 gGq[kGClasses][kMaxQ][kGDeg + 1] = {};
   __float128 gnuq[kGClasses] = {};
+  // strided layout of each class (the kernels evaluate it by Horner in
+  // phi^gstep): every nonzero degree of class c is gd0[c] + gstep[c] i, i < gK[c]
+  int gd0[kGClasses] = {};
+  int gstep[kGClasses] = {};
+  int gK[kGClasses] = {};
 };
 
 // f_eq_j(phi) of a non-polynomial model in long double (host checks, rest state)

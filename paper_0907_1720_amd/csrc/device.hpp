@@ -27,10 +27,12 @@ struct DevCoef {
   //   f_eq_j(phi) = sum_{c < gF} phi^gnu[c] sum_d G[c][j][d] phi^d
   int32_t gF;                // classes; 0 for polynomial equilibria
   int32_t groots;            // 1: every gnu is 1/2, 1/4 or 3/4 (square roots suffice, no log2)
+  int32_t gd0[kGCls];        // class c's nonzero degrees are gd0[c] + gstep[c] i
+  int32_t gstep[kGCls];
   double gnu[kGCls];         // gnu[0] = 0, the rest the fractional parts of the exponents
   double grest[8];           // f_rest_j subtracted at initialisation (FP32 deviations), else 0
-  double gwc[kGCls][7][kGRow];    // omega * G
-  double ginit[kGCls][7][kGRow];  // G
+  double gwc[kGCls][7][kGRow];    // omega * G[c][j][gd0[c] + gstep[c] i] at [c][j][i] (relaxation)
+  double ginit[kGCls][7][kGRow];  // G[c][j][d] (initialisation and boundary layers)
 };
 
 // Resident path: a job is the set of instances one workgroup advances side by
@@ -157,6 +159,14 @@ __device__ __forceinline__ double frac_pow(double nu, double phi, double lg, boo
   return exp2(nu * lg);
 }
 
+// x^k for a small wave-uniform k >= 0 (k - 1 products; x^0 = 1)
+__device__ __forceinline__ double int_pow(double x, int k) {
+  if (k == 0) return 1.0;
+  double r = x;
+  for (int i = 1; i < k; ++i) r *= x;
+  return r;
+}
+
 template <int Q, int D, int P, typename T, typename A>
 struct Relaxer {
   static constexpr int K = P == 0 ? D + 1 : (D + 1) / 2;   // coefficients per population
@@ -190,28 +200,36 @@ struct Relaxer {
     for (int j = 1; j < Q; ++j) s += (double)f[j];
     const A p = (A)s;
     if constexpr (P == 2) {
+      // class c contributes phi^(gnu[c] + gd0[c]) times a polynomial of
+      // degree <= D in phi^gstep[c] (Horner), so that only the degrees the
+      // class can hold are evaluated
       const DevCoef* __restrict__ g = cfp;
       const bool roots = g->groots != 0;
       const double lg = roots ? 0.0 : log2(s);
       double acc[Q];
+      {
+        const double w = int_pow(s, g->gstep[0]);
+        const double base = int_pow(s, g->gd0[0]);
 #pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        double a = g->gwc[0][j][D];
+        for (int j = 0; j < Q; ++j) {
+          double a = g->gwc[0][j][D];
 #pragma unroll
-        for (int d = D - 1; d >= 0; --d) a = __builtin_fma(a, s, g->gwc[0][j][d]);
-        acc[j] = a;
+          for (int d = D - 1; d >= 0; --d) a = __builtin_fma(a, w, g->gwc[0][j][d]);
+          acc[j] = base * a;
+        }
       }
       const int F = g->gF;
 #pragma unroll
       for (int cl = 1; cl < kGCls; ++cl) {
         if (cl < F) {
-          const double sc = frac_pow(g->gnu[cl], s, lg, roots);
+          const double w = int_pow(s, g->gstep[cl]);
+          const double base = frac_pow(g->gnu[cl], s, lg, roots) * int_pow(s, g->gd0[cl]);
 #pragma unroll
           for (int j = 0; j < Q; ++j) {
             double a = g->gwc[cl][j][D];
 #pragma unroll
-            for (int d = D - 1; d >= 0; --d) a = __builtin_fma(a, s, g->gwc[cl][j][d]);
-            acc[j] = __builtin_fma(sc, a, acc[j]);
+            for (int d = D - 1; d >= 0; --d) a = __builtin_fma(a, w, g->gwc[cl][j][d]);
+            acc[j] = __builtin_fma(base, a, acc[j]);
           }
         }
       }

@@ -8,7 +8,8 @@
 // Kernel variants of the relaxation polynomial: (padded degree D, parity P).
 // Dense (P = 0): D1Q5 KdV/KS/K(2,2) 5, cubic Pi 13, quartic Pi_1 up to 13;
 // D1Q7 Kawahara 7, cubic Pi 13, quartic Pi_1 19.  Odd (P = 1): mKdV 9.  Power
-// sums with real exponents (P = 2): integer degree 5, 7 or 11 per class.
+// sums with real exponents (P = 2): degree 2, 5, 7 or 11 of each class's
+// polynomial in phi^step (its strided layout).
 #define LBM_VARIANT_CASES \
   LBM_CASE(5, 0)          \
   LBM_CASE(7, 0)          \
@@ -19,6 +20,7 @@
   LBM_CASE(9, 1)          \
   LBM_CASE(13, 1)         \
   LBM_CASE(19, 1)         \
+  LBM_CASE(2, 2)          \
   LBM_CASE(5, 2)          \
   LBM_CASE(7, 2)          \
   LBM_CASE(11, 2)
@@ -38,7 +40,7 @@ namespace lbm {
 inline int padded_degree(int D, int parity) {
   const int dense[] = {5, 7, 9, 13, 19};
   const int odd[] = {5, 9, 13, 19};
-  const int power_sum[] = {5, 7, 11};
+  const int power_sum[] = {2, 5, 7, 11};
   if (parity == 0) {
     for (int v : dense)
       if (v >= D) return v;

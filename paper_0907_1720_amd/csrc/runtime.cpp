@@ -173,11 +173,12 @@ void fill_devcoef(const HostInst& h, DevCoef* c) {
       if (m.gnu[cl] != 0.5 && m.gnu[cl] != 0.25 && m.gnu[cl] != 0.75) c->groots = 0;
     for (int cl = 0; cl < m.gF; ++cl) {
       c->gnu[cl] = m.gnu[cl];
-      for (int j = 0; j < m.q; ++j)
-        for (int d = 0; d <= kGDeg && d < kGRow; ++d) {
-          c->gwc[cl][j][d] = m.gwG[cl][j][d];
-          c->ginit[cl][j][d] = m.gG[cl][j][d];
-        }
+      c->gd0[cl] = m.gd0[cl];
+      c->gstep[cl] = m.gstep[cl];
+      for (int j = 0; j < m.q; ++j) {
+        for (int d = 0; d <= kGDeg && d < kGRow; ++d) c->ginit[cl][j][d] = m.gG[cl][j][d];
+        for (int i = 0; i < m.gK[cl] && i < kGRow; ++i) c->gwc[cl][j][i] = m.gwG[cl][j][m.gd0[cl] + m.gstep[cl] * i];
+      }
     }
     if (h.f32) {
       c->phi_rest = m.phi_rest;
@@ -293,7 +294,9 @@ lbm_status prepare_one(const lbm_desc& d, HostInst* hp) {
     for (int p = 0; p <= h.mdl.D; p += 2)
       if (h.mdl.G[j][p] != 0.0) odd = false;
   const int parity = h.mdl.gF > 0 ? 2 : (odd ? 1 : 0);
-  const int kd = padded_degree(h.mdl.D, parity);
+  int kmax = 1;   // power sums: the longest strided class
+  for (int c = 0; c < h.mdl.gF; ++c) kmax = std::max(kmax, h.mdl.gK[c]);
+  const int kd = padded_degree(h.mdl.gF > 0 ? kmax - 1 : h.mdl.D, parity);
   // power sums initialise through their own tables; any init variant serves
   h.Dinit = h.mdl.gF > 0 ? padded_degree(1, 0) : padded_degree(h.mdl.D, 0);
   if (kd == 0 || h.Dinit == 0) return LBM_ERR_UNSUPPORTED;
