@@ -11,6 +11,11 @@ constexpr int kRow = 20;   // coefficient row length (max degree 19 + 1)
 constexpr int kGRow = 12;  // power-sum tables: integer degree <= 11 per class
 constexpr int kGCls = 4;   // power-sum tables: fractional-power classes
 
+// Slots per node in LDS: the lattice size, padded to an odd number (D1Q4 and
+// D1Q6 rows take 5 and 7 slots) so that consecutive nodes on consecutive lanes
+// fall on distinct LDS banks.
+constexpr int lds_stride(int q) { return q | 1; }
+
 // Per-problem constants on the device.
 struct DevCoef {
   double w0;                 // 1 - omega

@@ -118,9 +118,10 @@ __global__ __launch_bounds__(256) void k_stream(const T* __restrict__ fin, T* __
 
 // ---------------------------------------------------------------------------
 // In-LDS time steps with the alternating (AA) access pattern.  LDS holds node
-// x's populations together (S[x Q + j]; every population of a node is an
-// immediate offset from one address, and the odd strides of D1Q5 and D1Q7 keep
-// lanes free of bank conflicts -- D1Q4 and D1Q6 pay some).
+// x's populations together (S[x QS + j], QS = lds_stride(Q): every population
+// of a node is an immediate offset from one address, and an odd node stride
+// keeps consecutive lanes on distinct banks -- D1Q4 and D1Q6 rows are padded
+// to 5 and 7 slots, since an even stride gives 4- and 2-way bank conflicts).
 //   even step: node x reads S[x][j], writes f*_j to S[x][opp(j)]
 //   odd step:  node x reads S[x - e_j][opp(j)], writes f*_j to S[x + e_j][j]
 // Each node reads exactly the slots it writes, so one barrier per step
@@ -137,7 +138,7 @@ __device__ __forceinline__ int wrapn(int y, int n) {
 
 template <int Q, typename T, typename R>
 __device__ __forceinline__ void aa_even(T* __restrict__ S, int x, const R& r) {
-  T* p = S + x * Q;
+  T* p = S + x * lds_stride(Q);
   T f[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) f[j] = p[j];
@@ -148,8 +149,8 @@ __device__ __forceinline__ void aa_even(T* __restrict__ S, int x, const R& r) {
 
 template <int Q, typename T, typename R>
 __device__ __forceinline__ void aa_even2(T* __restrict__ S, int x, int y, const R& r) {
-  T* p = S + x * Q;
-  T* q = S + y * Q;
+  T* p = S + x * lds_stride(Q);
+  T* q = S + y * lds_stride(Q);
   T f[Q], h[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -168,32 +169,32 @@ __device__ __forceinline__ void aa_even2(T* __restrict__ S, int x, int y, const 
 template <int Q, typename T, typename R>
 __device__ __forceinline__ void aa_odd(T* __restrict__ S, int x, const R& r) {
   constexpr int H = Q / 2;
-  T* p = S + (x - H) * Q;
+  T* p = S + (x - H) * lds_stride(Q);
   T f[Q];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) f[j] = p[(H - velocity<Q>(j)) * Q + opposite<Q>(j)];
+  for (int j = 0; j < Q; ++j) f[j] = p[(H - velocity<Q>(j)) * lds_stride(Q) + opposite<Q>(j)];
   r(f);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) p[(H + velocity<Q>(j)) * Q + j] = f[j];
+  for (int j = 0; j < Q; ++j) p[(H + velocity<Q>(j)) * lds_stride(Q) + j] = f[j];
 }
 
 template <int Q, typename T, typename R>
 __device__ __forceinline__ void aa_odd2(T* __restrict__ S, int x, int y, const R& r) {
   constexpr int H = Q / 2;
-  T* p = S + (x - H) * Q;
-  T* q = S + (y - H) * Q;
+  T* p = S + (x - H) * lds_stride(Q);
+  T* q = S + (y - H) * lds_stride(Q);
   T f[Q], h[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    f[j] = p[(H - velocity<Q>(j)) * Q + opposite<Q>(j)];
-    h[j] = q[(H - velocity<Q>(j)) * Q + opposite<Q>(j)];
+    f[j] = p[(H - velocity<Q>(j)) * lds_stride(Q) + opposite<Q>(j)];
+    h[j] = q[(H - velocity<Q>(j)) * lds_stride(Q) + opposite<Q>(j)];
   }
   r(f);
   r(h);
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    p[(H + velocity<Q>(j)) * Q + j] = f[j];
-    q[(H + velocity<Q>(j)) * Q + j] = h[j];
+    p[(H + velocity<Q>(j)) * lds_stride(Q) + j] = f[j];
+    q[(H + velocity<Q>(j)) * lds_stride(Q) + j] = h[j];
   }
 }
 
@@ -202,10 +203,10 @@ template <int Q, typename T, typename R>
 __device__ __forceinline__ void aa_odd_wrap(T* __restrict__ S, int x, int n, const R& r) {
   T f[Q];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) f[j] = S[wrapn(x - velocity<Q>(j), n) * Q + opposite<Q>(j)];
+  for (int j = 0; j < Q; ++j) f[j] = S[wrapn(x - velocity<Q>(j), n) * lds_stride(Q) + opposite<Q>(j)];
   r(f);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) S[wrapn(x + velocity<Q>(j), n) * Q + j] = f[j];
+  for (int j = 0; j < Q; ++j) S[wrapn(x + velocity<Q>(j), n) * lds_stride(Q) + j] = f[j];
 }
 
 // every node x = lo + t + k B below hi, U (1 or 2) per iteration: two give
@@ -254,7 +255,7 @@ __device__ __forceinline__ void aa_bound_reset(T* __restrict__ S, const DevJobIn
   const int x = left ? b : n - 2 * nl + b;
   const int inner = left ? nl : n - 1 - nl;
   const double pb = reinterpret_cast<const double*>(ji.phib)[(size_t)step * 2 * nl + b];
-  auto at = [&](int y, int k) -> int { return odd ? wrapn(y - velocity<Q>(k), n) * Q + opposite<Q>(k) : y * Q + k; };
+  auto at = [&](int y, int k) -> int { return odd ? wrapn(y - velocity<Q>(k), n) * lds_stride(Q) + opposite<Q>(k) : y * lds_stride(Q) + k; };
   double neq = 0.0;
   if (ji.bkind == 2) {
     double s = 0.0, gj = 0.0;
@@ -295,7 +296,7 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
   const int seam0 = (r > 0 && r + 2 * H <= nt) ? r : 0;
   if (act)
     for (int j = 0; j < Q; ++j)
-      for (int x = t; x < n; x += nt) S[x * Q + j] = g[(int64_t)j * ji.stride + x];
+      for (int x = t; x < n; x += nt) S[x * lds_stride(Q) + j] = g[(int64_t)j * ji.stride + x];
   __syncthreads();
   for (int s = 0; s < steps; ++s) {
     if (act) {
@@ -321,7 +322,7 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
     const bool odd = (steps & 1) != 0;
     for (int j = 0; j < Q; ++j) {
       for (int x = t; x < n; x += nt) {
-        const T v = odd ? S[wrapn(x - velocity<Q>(j), n) * Q + opposite<Q>(j)] : S[x * Q + j];
+        const T v = odd ? S[wrapn(x - velocity<Q>(j), n) * lds_stride(Q) + opposite<Q>(j)] : S[x * lds_stride(Q) + j];
         bad |= !__builtin_isfinite(v);
         g[(int64_t)j * ji.stride + x] = v;
       }
@@ -439,7 +440,7 @@ __device__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* _
   constexpr int H = Q / 2;
   const int W = core + 2 * halo;
   for (int j = 0; j < Q; ++j)
-    for (int i = t; i < W; i += B) S[i * Q + j] = gin[(int64_t)j * stride + wrap_any(x0 - halo + i, n)];
+    for (int i = t; i < W; i += B) S[i * lds_stride(Q) + j] = gin[(int64_t)j * stride + wrap_any(x0 - halo + i, n)];
   __syncthreads();
   for (int s = 0; s < steps; ++s) {
     const int lo = s * H, hi = W - s * H;
@@ -453,7 +454,7 @@ __device__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* _
   const bool odd = (steps & 1) != 0;
   for (int j = 0; j < Q; ++j) {
     for (int i = halo + t; i < halo + core; i += B) {
-      const T v = odd ? S[(i - velocity<Q>(j)) * Q + opposite<Q>(j)] : S[i * Q + j];
+      const T v = odd ? S[(i - velocity<Q>(j)) * lds_stride(Q) + opposite<Q>(j)] : S[i * lds_stride(Q) + j];
       bad |= !__builtin_isfinite(v);
       gout[(int64_t)j * stride + x0 + (i - halo)] = v;
     }
@@ -542,7 +543,7 @@ __device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const D
   const int strip = Q * halo;   // values per strip
   const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
   for (int j = 0; j < Q; ++j)
-    for (int i = t; i < W; i += B) S[i * Q + j] = gin[(int64_t)j * stride + wrap_any(sl.x0 - halo + i, n)];
+    for (int i = t; i < W; i += B) S[i * lds_stride(Q) + j] = gin[(int64_t)j * stride + wrap_any(sl.x0 - halo + i, n)];
   if (t == 0) *bail = 0;
   __syncthreads();
   int done = 0, sb = 0;
@@ -563,7 +564,7 @@ __device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const D
     for (int idx = t; idx < 2 * strip; idx += B) {
       const int side = idx / strip, r = idx - side * strip, j = r / halo, h = r - j * halo;
       const int x = side == 0 ? halo + h : W - 2 * halo + h;
-      store_agent(mine + idx, S[x * Q + j]);
+      store_agent(mine + idx, S[x * lds_stride(Q) + j]);
     }
     wait_vm();
     __syncthreads();
@@ -589,9 +590,9 @@ __device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const D
     for (int idx = t; idx < 2 * strip; idx += B) {
       const int side = idx / strip, r = idx - side * strip, j = r / halo, h = r - j * halo;
       if (side == 0)
-        S[h * Q + j] = load_agent(lft + r);
+        S[h * lds_stride(Q) + j] = load_agent(lft + r);
       else
-        S[(W - halo + h) * Q + j] = load_agent(rgt + r);
+        S[(W - halo + h) * lds_stride(Q) + j] = load_agent(rgt + r);
     }
     __syncthreads();
   }
@@ -599,7 +600,7 @@ __device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const D
   const bool odd = (sb & 1) != 0;
   for (int j = 0; j < Q; ++j) {
     for (int i = halo + t; i < halo + sl.core; i += B) {
-      const T v = odd ? S[(i - velocity<Q>(j)) * Q + opposite<Q>(j)] : S[i * Q + j];
+      const T v = odd ? S[(i - velocity<Q>(j)) * lds_stride(Q) + opposite<Q>(j)] : S[i * lds_stride(Q) + j];
       bad |= !__builtin_isfinite(v);
       gout[(int64_t)j * stride + sl.x0 + (i - halo)] = v;
     }
@@ -618,7 +619,7 @@ void k_slab(const DevSlab* __restrict__ slabs, const DevTileInst* __restrict__ t
   const int me = blockIdx.x;
   const DevSlab sl = slabs[me];
   const DevTileInst ti = tinsts[sl.ti];
-  int* bail = reinterpret_cast<int*>(smem_raw + (size_t)(sl.core + 2 * halo) * Q * sizeof(T));
+  int* bail = reinterpret_cast<int*>(smem_raw + (size_t)(sl.core + 2 * halo) * lds_stride(Q) * sizeof(T));
   const T* gin = (ti.cur0 ? buf1 : buf0) + ti.off;
   T* gout = (ti.cur0 ? buf0 : buf1) + ti.off;
   slab_instance<Q, D, P, T, A>(S, bail, sl, ti, gin, gout, s_per, halo, xbuf, flags, me, coefs + ti.inst, status);

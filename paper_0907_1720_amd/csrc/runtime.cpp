@@ -463,7 +463,7 @@ lbm_status load_phi_one(lbm_batch_s* b, int i, const double* phi, int on_device)
 }
 
 bool fits_resident(const lbm_batch_s* b, const HostInst& h) {
-  return (size_t)h.q * h.n * elem_size(h) + resident_static_lds(h.q, h.prec, h.D) <= b->lim.lds_max;
+  return (size_t)lds_stride(h.q) * h.n * elem_size(h) + resident_static_lds(h.q, h.prec, h.D) <= b->lim.lds_max;
 }
 
 // The step-block graph of instance i for its current buffer, built on first use
@@ -548,7 +548,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   size_t res_bytes = 0;
   for (int i = 0; i < count; ++i)
     if (steps[i] && b->path == 0 && fits_resident(b, b->inst[i]))
-      res_bytes += (size_t)b->inst[i].q * b->inst[i].n * elem_size(b->inst[i]);
+      res_bytes += (size_t)lds_stride(b->inst[i].q) * b->inst[i].n * elem_size(b->inst[i]);
   const bool latency = b->path == 0 && b->res_grid == 0 && 4 * res_bytes < (size_t)b->lim.cus * b->lim.lds_max;
   const int slab_wgs = b->tile_wgs > 0 ? b->tile_wgs : 2;
   for (int i = 0; i < count; ++i) {
@@ -594,7 +594,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       std::vector<int> g = group.second;
       const size_t es = pr ? sizeof(float) : sizeof(double);
       const int q = std::get<0>(group.first);
-      auto bytes_of = [&](int i) { return ((size_t)q * b->inst[i].n * es + 15) / 16 * 16; };
+      auto bytes_of = [&](int i) { return ((size_t)lds_stride(q) * b->inst[i].n * es + 15) / 16 * 16; };
       // jobs: first-fit decreasing bin packing of equal-step instances into a
       // workgroup's LDS share (half the LDS, or the largest instance)
       // jobs hold instances of one variant and one step count
@@ -730,13 +730,13 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const std::vector<int>& g = group.second;
       const int q = qq, H = q / 2;
       const size_t es = pr ? sizeof(float) : sizeof(double);
-      const int W = (int)((b->lim.lds_max / (size_t)wgs - 16) / (q * es));
+      const int W = (int)((b->lim.lds_max / (size_t)wgs - 16) / (lds_stride(q) * es));
       int sp = b->tile_steps > 0 ? (b->tile_steps + 1) / 2 * 2 : 16;   // even: strips in natural layout
       while (sp > 2 && W - 2 * sp * H < 2 * sp * H) sp -= 2;
       const int halo = sp * H;
       const int cmax = W - 2 * halo;
       const int block = std::min(1024, std::max(64, (W / 2 + 63) / 64 * 64));
-      const size_t lds = (size_t)W * q * es + 16;
+      const size_t lds = (size_t)W * lds_stride(q) * es + 16;
       int per_cu = 0;
       if (cmax < halo || slab_occupancy(q, pr, code, block, lds, &per_cu) != hipSuccess) per_cu = 0;
       const int capacity = std::min(per_cu * b->lim.cus, kMaxSlabs);
@@ -853,7 +853,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int q = qq, H = q / 2;
       const size_t es = pr ? sizeof(float) : sizeof(double);
       const int wgs = b->tile_wgs > 0 ? b->tile_wgs : 2;
-      const int W = (int)(b->lim.lds_max / (size_t)wgs / (q * es));
+      const int W = (int)(b->lim.lds_max / (size_t)wgs / (lds_stride(q) * es));
       // tile core: as wide as the LDS share allows, but narrow enough that the
       // group yields about 4 tiles per CU (a few large instances would otherwise
       // leave most CUs idle); halo / core kept below 1/4
@@ -889,7 +889,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       G.ntiles = (int)tvec.size() - G.first;
       G.tcount = tin_used - G.tfirst;
       G.launches = (int)((maxsteps + sp - 1) / sp);
-      G.lds = (size_t)q * (maxcore + 2 * halo) * es;
+      G.lds = (size_t)lds_stride(q) * (maxcore + 2 * halo) * es;
       // two or more nodes per thread
       G.block = std::min(kBlock, std::max(64, ((maxcore + 2 * halo) / 2 + 63) / 64 * 64));
       tgroups.push_back(G);

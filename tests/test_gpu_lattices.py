@@ -105,7 +105,7 @@ def test_even_lattice_fp64_all_paths(name, n):
     want = O.run(p, phi0, steps)
     ref = None
     for path in PATHS:
-        if path == lbm.PATH_RESIDENT and p.lattice() * n * 8 + 64 > 160 * 1024:
+        if path == lbm.PATH_RESIDENT and (p.lattice() | 1) * n * 8 + 64 > 160 * 1024:
             continue
         tiling = (8, 8) if path == lbm.PATH_SLAB else (0, 0)
         got = _run(p, phi0, steps, path, tiling)
