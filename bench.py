@@ -358,6 +358,7 @@ def main():
                           "kernel_ms": r32["kernel_ms"], "status_ok": r32["status_ok"]}))
         return
     r64 = run(W.F64)
+    r32a = run(W.F32_DEV_ARITH32)
     lg = large_grids()
     hs = hbm_stream()
     nx = next_rows()
@@ -413,6 +414,9 @@ def main():
                    "node_updates_per_step": r32["nu_pass"]},
         "fp64_batched": {"value": r64["nu_per_s"], "ms_per_step": r64["wall_s"] / args.steps * 1e3,
                          "kernel_ms": float(np.mean(r64["kernel_ms"])), "autotune": r64["tuning"]},
+        "fp32_arith_batched": {"value": r32a["nu_per_s"], "ms_per_step": r32a["wall_s"] / args.steps * 1e3,
+                               "kernel_ms": float(np.mean(r32a["kernel_ms"])),
+                               "precision": "FP32 deviation storage and FP32 relaxation (LBM_F32_DEV_ARITH32)"},
         "autotune": r32["tuning"],
         "plain_fp64": {"value": plain, "sample_instances": int(len(sample)),
                        "path": "one fused collide+stream launch per step (64-step blocks replayed from a HIP graph), "
@@ -424,7 +428,7 @@ def main():
                                     "Kawahara/K(2,2) N in {2048, 16384} (512 instances, 500 steps), device time",
                         **lg},
         "next_rows": nx,
-        "status_ok": bool(r32["status_ok"] and r64["status_ok"]),
+        "status_ok": bool(r32["status_ok"] and r64["status_ok"] and r32a["status_ok"]),
         "roofline": roofline,
         "serving": srv_out,
     }
