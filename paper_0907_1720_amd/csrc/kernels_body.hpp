@@ -431,7 +431,7 @@ __device__ __forceinline__ int wrap_any(int y, int n) {
 }
 
 template <int Q, int D, int P, typename T, typename A>
-__device__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* __restrict__ gout, int n,
+__device__ __forceinline__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* __restrict__ gout, int n,
                               int stride, int x0, int core, int halo, int steps,
                               const DevCoef* __restrict__ cf, int* __restrict__ status) {
   const int B = blockDim.x;
@@ -442,12 +442,15 @@ __device__ void tile_instance(T* __restrict__ S, const T* __restrict__ gin, T* _
   for (int j = 0; j < Q; ++j)
     for (int i = t; i < W; i += B) S[i * lds_stride(Q) + j] = gin[(int64_t)j * stride + wrap_any(x0 - halo + i, n)];
   __syncthreads();
+  // two nodes per iteration, except for the power sums (whose per-node
+  // arithmetic already fills the registers)
+  constexpr int U = P == 2 ? 1 : 2;
   for (int s = 0; s < steps; ++s) {
     const int lo = s * H, hi = W - s * H;
     if ((s & 1) == 0)
-      aa_sweep<Q, false, 2>(S, lo, hi, t, B, relax);
+      aa_sweep<Q, false, U>(S, lo, hi, t, B, relax);
     else
-      aa_sweep<Q, true, 2>(S, lo, hi, t, B, relax);
+      aa_sweep<Q, true, U>(S, lo, hi, t, B, relax);
     __syncthreads();
   }
   bool bad = false;
