@@ -127,3 +127,56 @@ def test_poisson_arrivals_report_latency():
     assert out["nonfinite"] == 0
     assert 0.0 < out["p50_latency_s"] <= out["p99_latency_s"]
     assert out["node_updates"] == sum(r.problem.n * r.steps for r in reqs)
+
+
+def test_extension_models_served_alongside_the_mix():
+    """Requests with real powers of phi (D1Q5, FP64 and FP32 storage) and on the
+    lattices without rest velocity (D1Q4, D1Q6) share server rounds with the
+    config-5 families; grids up to 4096 nodes take the latency-regime slabs or
+    tiles.  Each result equals its own solve bit for bit; one request per new
+    kind is checked against the oracle."""
+    exts = []
+    for i in (3, 11):
+        for prec in (W.F64, W.F32_DEV):
+            x = W.power_batch_instance(i, prec=prec, steps=300 + 37 * i)
+            exts.append(x)
+    for q in (4, 6):
+        for i in (0, 5):
+            exts.append(W.even_lattice_instance(i, q, steps=250 + 19 * i))
+    reqs = _requests(10, n_max=4096, steps_max=900, start=500)
+    probs = [r.problem for r in reqs] + [x.problem for x in exts]
+    phis = [r.phi0 for r in reqs] + [x.phi0 for x in exts]
+    steps = [r.steps for r in reqs] + [x.steps for x in exts]
+    srv = lbm.Server(256 << 20, max_slots=32, max_n=4096, block_steps=200)
+    ids = [srv.submit(p, f, s) for p, f, s in zip(probs, phis, steps)]
+    got = {}
+    rounds = 0
+    while len(got) < len(ids):
+        srv.step()
+        rounds += 1
+        assert rounds < 10000
+        for k, rid in enumerate(ids):
+            if k not in got:
+                res = srv.poll(rid)
+                if res is not None:
+                    got[k] = res
+    srv.close()
+    checked = set()
+    for k, (p, f, s) in enumerate(zip(probs, phis, steps)):
+        phi, st = got[k]
+        assert st == lbm.OK, (k, p.name)
+        solo = lbm.Solver(p)
+        solo.load_phi(f)
+        solo.advance(s)
+        ref = solo.read_phi()
+        solo.close()
+        say("case served extension", k, p.name, p.lattice(), p.n, s)
+        assert np.array_equal(phi, ref), (k, p.name, p.n)
+        key = (p.name, p.lattice(), p.prec)
+        if k >= len(reqs) and key not in checked:
+            checked.add(key)
+            want = O.run(dataclasses.replace(p, prec=W.F64), f, s)
+            tol = 1e-12 if p.prec == W.F64 else 1e-4
+            err = rel2(phi, want)
+            say("    vs oracle", f"{err:.2e}")
+            assert err <= tol, (k, p.name, err)
