@@ -94,13 +94,26 @@ def algorithmic_flops_per_nu(G: np.ndarray) -> int:
 
 def algorithmic_flops_power_sum(nu: np.ndarray, G: np.ndarray) -> int:
     """Arithmetic of one node update for an equilibrium with real powers,
-    f_eq_j = sum_c phi^nu_c sum_d G[c, j, d] phi^d (G: F x q x (D+1)): the phi
-    sum (q - 1 adds), per population a Horner over each class's degree, one FMA
-    per further class, the BGK FMA.  The powers phi^nu (square roots, or
-    exp2/log2) are not counted."""
+    f_eq_j = sum_c phi^nu_c sum_d G[c, j, d] phi^d (G: F x q x (D+1)), counted
+    for the cheapest evaluation of each class: its nonzero degrees lie on
+    d0 + s i (i < K), so phi^(nu_c + d0) times a Horner of K terms in phi^s.
+    Per node: the phi sum (q - 1 adds) and, per class, the products forming
+    phi^s and phi^d0 (s - 1 and d0 - 1 multiplies, one more to apply phi^nu_c);
+    per population and class K - 1 FMAs and one FMA (or multiply) applying the
+    class factor; per population the BGK FMA.  The powers phi^nu (square roots,
+    or exp2/log2) are not counted."""
     F, q = G.shape[0], G.shape[1]
-    deg = [max((d for d in range(G.shape[2]) if np.any(G[c, :, d])), default=0) for c in range(F)]
-    return (q - 1) + q * (sum(2 * d for d in deg) + 2 * (F - 1) + 2)
+    flops = q - 1
+    for c in range(F):
+        degs = [d for d in range(G.shape[2]) if np.any(G[c, :, d])]
+        if not degs:
+            continue
+        d0 = degs[0]
+        s = int(np.gcd.reduce([d - d0 for d in degs[1:]])) if len(degs) > 1 else 1
+        K = (degs[-1] - d0) // s + 1
+        flops += max(s - 1, 0) + max(d0 - 1, 0) + (1 if c > 0 else 0)
+        flops += q * (2 * (K - 1) + 2)
+    return flops + 2 * q
 
 
 def _oracle_one(args):
@@ -121,7 +134,26 @@ def cpu_baseline(sample: int = 32, steps: int = LB_STEPS):
     nu = sum(r[0] for r in res)
     return {"value": nu / wall, "unit": "node-updates/s", "cores": workers, "kind": "oracle",
             "sample": f"instances 0..{sample - 1} of the 4096-instance batch, {steps} steps each, "
-                      f"numpy FP64 oracle, one process per core ({workers} processes), wall clock"}
+                      f"numpy FP64 oracle, one process per core ({workers} processes), wall clock",
+            "host": host_cpu()}
+
+
+def host_cpu() -> dict:
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = None
+    return {"model": model, "logical_cpus": os.cpu_count(), "affinity_cpus": allowed}
 
 
 def main():
