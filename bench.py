@@ -333,6 +333,28 @@ def main():
             "alu_frac": fl / (ms * 1e-3) / 1e12 / PEAK_VALU_TFLOPS,
             "tau_opt": float(taus[int(np.argmin(err))]), "E_at_tau_opt": float(min(err)),
             "status_ok": all(r[1] == lbm.OK for r in res)}
+        # the same sweep with the boundary values evaluated on the device from the
+        # front's closed form (no host rows): wall clock of the call, rows included
+        wv = W.table8_wave()
+        wave = lbm.make_wave(wv["shape"], wv["a"], wv["b"], wv["p"], wv["k"], wv["xc"], wv["c"], float(x[0]))
+        b = lbm.Batch(probs, stream=stream.cuda_stream)
+        b.load_phi([ex(x, 0.0)] * len(probs))
+        b.advance_bounded_wave([wave] * len(probs), 200)        # warm-up
+        b.load_phi([ex(x, 0.0)] * len(probs))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.advance_bounded_wave([wave] * len(probs), steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        msw = b.last_advance_ms()
+        resw = [b.read_phi(i) for i in range(len(probs))]
+        b.close()
+        errw = [float(np.sum(np.abs(r[0] - ex(x, steps * p0.dt))) / np.sum(np.abs(ex(x, steps * p0.dt))))
+                if r[1] == lbm.OK else float("inf") for r in resw]
+        out["bounded_tau_sweep_device_rows"] = {
+            "workload": "the same sweep, boundary rows evaluated on the device from the front's closed form",
+            "kernel_ms": msw, "wall_ms": wall * 1e3, "node_updates_per_s": nu / wall,
+            "E_at_tau_opt": float(errw[int(np.argmin(err))]), "status_ok": all(r[1] == lbm.OK for r in resw)}
         # the same problem on the per-step streaming path (one collide+stream and
         # one boundary launch per step)
         s = lbm.Solver(p0, stream=stream.cuda_stream)

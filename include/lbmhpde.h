@@ -179,6 +179,39 @@ lbm_status lbm_advance(lbm_problem h, int64_t steps);
    sizes. */
 lbm_status lbm_advance_bounded(lbm_problem h, int64_t steps, const double* phib, int32_t layers);
 
+/* Exact solutions of travelling-wave form for the bounded kinds, evaluated on
+   the device (the closed forms of the examples of Sec. IV: the tanh
+   polynomials of the Burgers-type equations, sech^2 and sech^4 solitary
+   waves, the KdV-Burgers front; also K(2,2) compactons):
+     phi*(x, t) = a + b h(z)^p + d h(z)^r,  z = k (x - xc - c t),
+   h = 1/cosh (SECH), tanh (TANH), 1/(1 + e^z) (LOGISTIC), or cos on
+   |z| <= pi/2 and 0 outside (COS, the compacton support); x = x_first + i dx
+   at node i; t = t0 + s dt after step s (t0: the time of the state when the
+   call starts).  p, r >= 0 (integers for TANH, whose h may be negative);
+   every parameter finite.  Plain data; layout fixed. */
+typedef enum { LBM_WAVE_SECH = 1, LBM_WAVE_TANH = 2, LBM_WAVE_LOGISTIC = 3, LBM_WAVE_COS = 4 } lbm_wave_shape;
+typedef struct {
+  int32_t shape;         /* lbm_wave_shape */
+  int32_t pad_;
+  double a, b, p;        /* phi* = a + b h(z)^p + d h(z)^r */
+  double d, r;
+  double k, xc, c;       /* z = k (x - xc - c t) */
+  double x_first;        /* x of node 0 */
+  double t0;             /* time of the state when the call starts */
+} lbm_wave;
+
+/* lbm_advance_bounded with the boundary values phi*(x_b, t0 + s dt) of `w`
+   computed on the device (one row of 2 layers values per step, in device
+   memory the library owns) instead of copied from the host; same paths,
+   same layer rules.  INVALID_ARG for an invalid wave (shape, p, a non-finite
+   parameter) before any device work. */
+lbm_status lbm_advance_bounded_wave(lbm_problem h, int64_t steps, const lbm_wave* w, int32_t layers);
+
+/* The boundary rows lbm_advance_bounded_wave(h, steps, w, layers) would use,
+   evaluated on the device and copied to out (host, steps * 2 layers doubles,
+   in the phib layout of lbm_advance_bounded).  Synchronises. */
+lbm_status lbm_wave_rows(lbm_problem h, int64_t steps, const lbm_wave* w, int32_t layers, double* out);
+
 /* phi = sum_j f_j (zeroth moment, FP64) into n doubles on the host or device.
    Synchronises; returns LBM_ERR_NONFINITE (after writing) if any value is NaN/Inf. */
 lbm_status lbm_read_phi(lbm_problem h, double* out, int out_on_device);
@@ -234,6 +267,10 @@ lbm_status lbm_batch_advance(lbm_batch b, const int64_t* steps);
    fit a workgroup's LDS or another path is forced.  A tau sweep of one bounded
    problem is one call. */
 lbm_status lbm_batch_advance_bounded(lbm_batch b, int64_t steps, const double* const* phib, int32_t layers);
+/* As lbm_batch_advance_bounded with bounded instance i's rows evaluated on the
+   device from waves[i] (see lbm_wave; entries of periodic instances are
+   ignored).  waves: host array of one lbm_wave per instance. */
+lbm_status lbm_batch_advance_bounded_wave(lbm_batch b, int64_t steps, const lbm_wave* waves, int32_t layers);
 
 /* phi of instance i into n host doubles; *inst_status (nullable) receives
    LBM_OK or LBM_ERR_NONFINITE for that instance alone.  Synchronises. */

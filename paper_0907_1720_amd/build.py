@@ -45,16 +45,18 @@ LATTICES = (4, 5, 6, 7)
 
 
 def build(verbose: bool = False) -> str:
-    """Compiles the host sources, the read-out/launcher unit and one kernel unit
-    per lattice size (kernels_q.hip with LBM_Q = 4..7) in parallel, then links."""
+    """Compiles the host sources, the read-out/launcher unit, the boundary-wave
+    unit and one kernel unit per lattice size (kernels_q.hip with LBM_Q = 4..7)
+    in parallel, then links."""
     os.makedirs(BUILD, exist_ok=True)
     inc = [f"-I{INCLUDE}", f"-I{CSRC}"]
     steps = []
     for src in ("coeffs.cpp", "runtime.cpp"):
         obj = os.path.join(BUILD, src + ".o")
         steps.append((obj, [CLANG] + HOST_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj]))
-    obj = os.path.join(BUILD, "kernels.hip.o")
-    steps.append((obj, [HIPCC] + DEVICE_FLAGS + inc + ["-c", os.path.join(CSRC, "kernels.hip"), "-o", obj]))
+    for src in ("kernels.hip", "kernels_wave.hip"):
+        obj = os.path.join(BUILD, src + ".o")
+        steps.append((obj, [HIPCC] + DEVICE_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj]))
     for q in LATTICES:
         obj = os.path.join(BUILD, f"kernels_q{q}.hip.o")
         steps.append((obj, [HIPCC] + DEVICE_FLAGS + inc + [f"-DLBM_Q={q}", "-c",

@@ -16,6 +16,7 @@
 
 #include "coeffs.hpp"
 #include "kernels.hpp"
+#include "wave.hpp"
 #include "lbmhpde.h"
 
 using namespace lbm;
@@ -1347,11 +1348,44 @@ lbm_status lbm_advance(lbm_problem h, int64_t steps) {
   return advance(h->b, &steps);
 }
 
+}  // extern "C"
+
 namespace {
+// Where the boundary rows of a bounded call come from: host arrays (copied),
+// or travelling waves evaluated on the device.
+struct RowSource {
+  const double* const* host = nullptr;   // per instance
+  const lbm_wave* waves = nullptr;       // per instance
+};
+
+bool valid_wave(const lbm_wave* w) {
+  if (!w) return false;
+  if (w->shape < LBM_WAVE_SECH || w->shape > LBM_WAVE_COS) return false;
+  const double v[] = {w->a, w->b, w->p, w->d, w->r, w->k, w->xc, w->c, w->x_first, w->t0};
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  if (w->p < 0.0 || w->r < 0.0) return false;
+  // tanh may be negative: integer exponents only
+  if (w->shape == LBM_WAVE_TANH && (w->p != std::floor(w->p) || w->r != std::floor(w->r))) return false;
+  return true;
+}
+
+// rows [steps][2 layers] of instance i into device memory dst (on b->stream)
+lbm_status fill_rows(lbm_batch_s* b, int i, const RowSource& src, double* dst, int64_t steps, int layers) {
+  const HostInst& h = b->inst[i];
+  const size_t rows = (size_t)steps * 2 * layers;
+  if (src.host) {
+    LBM_HIP(hipMemcpy(dst, src.host[i], sizeof(double) * rows, hipMemcpyHostToDevice));
+  } else {
+    LBM_HIP(launch_wave_rows(dst, steps, layers, h.n, h.desc.dx, h.desc.dt, src.waves[i], b->stream));
+  }
+  return LBM_OK;
+}
+
 // Bounded instances of a batch advance `steps` (<= kMaxStepsPerLaunch) steps on
 // the resident path, their boundary layers reset in LDS after every step;
-// phib[i]: host rows [steps][2 layers] of bounded instance i.
-lbm_status advance_bounded_resident(lbm_batch_s* b, int64_t steps, const double* const* phib, int layers) {
+// rows [steps][2 layers] of bounded instance i from `src`.
+lbm_status advance_bounded_resident(lbm_batch_s* b, int64_t steps, const RowSource& src, int layers) {
   const int count = (int)b->inst.size();
   int nb = 0;
   for (int i = 0; i < count; ++i) nb += b->inst[i].desc.bc != LBM_BC_PERIODIC;
@@ -1370,7 +1404,8 @@ lbm_status advance_bounded_resident(lbm_batch_s* b, int64_t steps, const double*
   for (int i = 0, k = 0; i < count; ++i) {
     if (b->inst[i].desc.bc == LBM_BC_PERIODIC) continue;
     double* dst = b->bound + (size_t)k++ * rows;
-    LBM_HIP(hipMemcpy(dst, phib[i], sizeof(double) * rows, hipMemcpyHostToDevice));
+    lbm_status s = fill_rows(b, i, src, dst, steps, layers);
+    if (s != LBM_OK) return s;
     b->bnd_ptr[i] = (uint64_t)(uintptr_t)dst;
   }
   b->bnd_active = true;
@@ -1380,10 +1415,8 @@ lbm_status advance_bounded_resident(lbm_batch_s* b, int64_t steps, const double*
   b->bnd_active = false;
   return s;
 }
-}  // namespace
-
-lbm_status lbm_batch_advance_bounded(lbm_batch b, int64_t steps, const double* const* phib, int32_t layers) {
-  if (!b || steps < 0 || steps > kMaxStepsPerLaunch) return LBM_ERR_INVALID_ARG;
+lbm_status batch_advance_bounded(lbm_batch_s* b, int64_t steps, const RowSource& src, int layers) {
+  if (steps < 0 || steps > kMaxStepsPerLaunch) return LBM_ERR_INVALID_ARG;
   int hmax = 0;
   for (const HostInst& h : b->inst)
     if (h.desc.bc != LBM_BC_PERIODIC) hmax = std::max(hmax, h.q / 2);
@@ -1392,41 +1425,53 @@ lbm_status lbm_batch_advance_bounded(lbm_batch b, int64_t steps, const double* c
   for (size_t i = 0; i < b->inst.size(); ++i) {
     const HostInst& h = b->inst[i];
     if (h.desc.bc == LBM_BC_PERIODIC) continue;
-    if (steps > 0 && (!phib || !phib[i])) return LBM_ERR_INVALID_ARG;
+    if (src.host && steps > 0 && !src.host[i]) return LBM_ERR_INVALID_ARG;
+    if (src.waves && !valid_wave(&src.waves[i])) return LBM_ERR_INVALID_ARG;
     if (h.n < 2 * layers + 2) return LBM_ERR_INVALID_ARG;
   }
   if (steps == 0) return LBM_OK;
-  return advance_bounded_resident(b, steps, phib, layers);
+  return advance_bounded_resident(b, steps, src, layers);
 }
 
-lbm_status lbm_advance_bounded(lbm_problem h, int64_t steps, const double* phib, int32_t layers) {
-  if (!h || steps < 0 || (steps > 0 && !phib)) return LBM_ERR_INVALID_ARG;
-  lbm_batch_s* b = h->b;
-  HostInst& in = b->inst[0];
-  if (in.desc.bc != LBM_BC_DIRICHLET_EQ && in.desc.bc != LBM_BC_DIRICHLET_NEE) return LBM_ERR_INVALID_ARG;
-  const int H = in.q / 2;
-  if (layers == 0) layers = H;
-  if (layers < H || layers > 32 || in.n < 2 * layers + 2) return LBM_ERR_INVALID_ARG;
-  if (steps == 0) return LBM_OK;
-  // LDS-resident unless the streaming path is asked for or the state does not fit
-  if ((b->path == 0 || b->path == 2) && fits_resident(b, in) && steps <= kMaxStepsPerLaunch) {
-    const double* rows[1] = {phib};
-    return advance_bounded_resident(b, steps, rows, layers);
-  }
-  lbm_status s = ensure_second_buffer(b, in.f32);
-  if (s != LBM_OK) return s;
-  const size_t need = (size_t)steps * 2 * layers;
+// device rows buffer of at least steps * 2 layers doubles (b->bound), no
+// earlier launch still reading it
+lbm_status bound_rows_buffer(lbm_batch_s* b, size_t need) {
+  LBM_HIP(hipStreamSynchronize(b->stream));
   if (need > b->bound_cap) {
-    LBM_HIP(hipStreamSynchronize(b->stream));   // earlier boundary launches may still read the old buffer
     hipFree(b->bound);
     b->bound = nullptr;
     b->bound_cap = 0;
     if (hipMalloc(&b->bound, sizeof(double) * need) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
     b->bound_cap = need;
   }
-  // a synchronous copy: the previous call's launches have read the buffer by the time it lands
-  LBM_HIP(hipStreamSynchronize(b->stream));
-  LBM_HIP(hipMemcpy(b->bound, phib, sizeof(double) * need, hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+// single bounded problem: `layers` resolved and checked against the problem
+lbm_status bounded_layers(const HostInst& in, int32_t* layers) {
+  if (in.desc.bc != LBM_BC_DIRICHLET_EQ && in.desc.bc != LBM_BC_DIRICHLET_NEE) return LBM_ERR_INVALID_ARG;
+  const int H = in.q / 2;
+  if (*layers == 0) *layers = H;
+  if (*layers < H || *layers > 32 || in.n < 2 * *layers + 2) return LBM_ERR_INVALID_ARG;
+  return LBM_OK;
+}
+
+lbm_status advance_bounded_one(lbm_batch_s* b, int64_t steps, const RowSource& src, int32_t layers) {
+  HostInst& in = b->inst[0];
+  lbm_status s = bounded_layers(in, &layers);
+  if (s != LBM_OK) return s;
+  if (src.waves && !valid_wave(src.waves)) return LBM_ERR_INVALID_ARG;
+  if (steps == 0) return LBM_OK;
+  // LDS-resident unless the streaming path is asked for or the state does not fit
+  if ((b->path == 0 || b->path == 2) && fits_resident(b, in) && steps <= kMaxStepsPerLaunch)
+    return advance_bounded_resident(b, steps, src, layers);
+  s = ensure_second_buffer(b, in.f32);
+  if (s != LBM_OK) return s;
+  const size_t need = (size_t)steps * 2 * layers;
+  s = bound_rows_buffer(b, need);
+  if (s != LBM_OK) return s;
+  s = fill_rows(b, 0, src, b->bound, steps, layers);
+  if (s != LBM_OK) return s;
   const int kind = in.desc.bc == LBM_BC_DIRICHLET_EQ ? 1 : 2;
   LBM_HIP(hipEventRecord(b->ev0, b->stream));
   for (int64_t t = 0; t < steps; ++t) {
@@ -1438,6 +1483,58 @@ lbm_status lbm_advance_bounded(lbm_problem h, int64_t steps, const double* phib,
   }
   LBM_HIP(hipEventRecord(b->ev1, b->stream));
   in.steps_done += steps;
+  return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_advance_bounded(lbm_batch b, int64_t steps, const double* const* phib, int32_t layers) {
+  if (!b) return LBM_ERR_INVALID_ARG;
+  for (const HostInst& h : b->inst)
+    if (h.desc.bc != LBM_BC_PERIODIC && steps > 0 && !phib) return LBM_ERR_INVALID_ARG;
+  RowSource src;
+  src.host = phib;
+  return batch_advance_bounded(b, steps, src, layers);
+}
+
+lbm_status lbm_batch_advance_bounded_wave(lbm_batch b, int64_t steps, const lbm_wave* waves, int32_t layers) {
+  if (!b || !waves) return LBM_ERR_INVALID_ARG;
+  RowSource src;
+  src.waves = waves;
+  return batch_advance_bounded(b, steps, src, layers);
+}
+
+lbm_status lbm_advance_bounded(lbm_problem h, int64_t steps, const double* phib, int32_t layers) {
+  if (!h || steps < 0 || (steps > 0 && !phib)) return LBM_ERR_INVALID_ARG;
+  const double* rows[1] = {phib};
+  RowSource src;
+  src.host = rows;
+  return advance_bounded_one(h->b, steps, src, layers);
+}
+
+lbm_status lbm_advance_bounded_wave(lbm_problem h, int64_t steps, const lbm_wave* w, int32_t layers) {
+  if (!h || steps < 0 || !w) return LBM_ERR_INVALID_ARG;
+  RowSource src;
+  src.waves = w;
+  return advance_bounded_one(h->b, steps, src, layers);
+}
+
+lbm_status lbm_wave_rows(lbm_problem h, int64_t steps, const lbm_wave* w, int32_t layers, double* out) {
+  if (!h || steps < 0 || !w || (steps > 0 && !out) || !valid_wave(w)) return LBM_ERR_INVALID_ARG;
+  lbm_batch_s* b = h->b;
+  lbm_status s = bounded_layers(b->inst[0], &layers);
+  if (s != LBM_OK) return s;
+  if (steps == 0) return LBM_OK;
+  const size_t need = (size_t)steps * 2 * layers;
+  s = bound_rows_buffer(b, need);
+  if (s != LBM_OK) return s;
+  RowSource src;
+  src.waves = w;
+  s = fill_rows(b, 0, src, b->bound, steps, layers);
+  if (s != LBM_OK) return s;
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  LBM_HIP(hipMemcpy(out, b->bound, sizeof(double) * need, hipMemcpyDeviceToHost));
   return LBM_OK;
 }
 

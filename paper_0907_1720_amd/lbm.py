@@ -45,6 +45,40 @@ class LbmDesc(ctypes.Structure):
     ]
 
 
+WAVE_SECH, WAVE_TANH, WAVE_LOGISTIC, WAVE_COS = 1, 2, 3, 4
+
+
+class LbmWave(ctypes.Structure):
+    """phi*(x, t) = a + b h(z)^p + d h(z)^r, z = k (x - xc - c t)
+    (include/lbmhpde.h, lbm_wave)."""
+    _fields_ = [
+        ("shape", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("a", ctypes.c_double),
+        ("b", ctypes.c_double),
+        ("p", ctypes.c_double),
+        ("d", ctypes.c_double),
+        ("r", ctypes.c_double),
+        ("k", ctypes.c_double),
+        ("xc", ctypes.c_double),
+        ("c", ctypes.c_double),
+        ("x_first", ctypes.c_double),
+        ("t0", ctypes.c_double),
+    ]
+
+
+WAVE_SHAPES = {"sech": WAVE_SECH, "tanh": WAVE_TANH, "logistic": WAVE_LOGISTIC, "cos": WAVE_COS}
+
+
+def make_wave(shape, a: float, b: float, p: float, k: float, xc: float, c: float, x_first: float,
+              t0: float = 0.0, d: float = 0.0, r: float = 0.0) -> LbmWave:
+    """An LbmWave; `shape` is an lbm_wave_shape value or its name ("sech", "tanh",
+    "logistic", "cos")."""
+    code = WAVE_SHAPES[shape] if isinstance(shape, str) else int(shape)
+    return LbmWave(code, 0, float(a), float(b), float(p), float(d), float(r), float(k), float(xc), float(c),
+                   float(x_first), float(t0))
+
+
 class LbmTuning(ctypes.Structure):
     _fields_ = [
         ("path", ctypes.c_int32),
@@ -91,6 +125,8 @@ def library() -> ctypes.CDLL:
         "lbm_load_phi": (I32, [P, P, I32]),
         "lbm_advance": (I32, [P, I64]),
         "lbm_advance_bounded": (I32, [P, I64, P, I32]),
+        "lbm_advance_bounded_wave": (I32, [P, I64, P, I32]),
+        "lbm_wave_rows": (I32, [P, I64, P, I32, P]),
         "lbm_read_phi": (I32, [P, P, I32]),
         "lbm_sum_phi": (I32, [P, P]),
         "lbm_state_bytes": (I32, [P, P]),
@@ -104,6 +140,7 @@ def library() -> ctypes.CDLL:
         "lbm_batch_load_phi": (I32, [P, P]),
         "lbm_batch_advance": (I32, [P, P]),
         "lbm_batch_advance_bounded": (I32, [P, I64, P, I32]),
+        "lbm_batch_advance_bounded_wave": (I32, [P, I64, P, I32]),
         "lbm_batch_read_phi": (I32, [P, I32, P, P]),
         "lbm_batch_last_advance_ms": (I32, [P, P]),
         "lbm_batch_set_path": (I32, [P, I32]),
@@ -262,6 +299,20 @@ class Solver:
             raise ValueError("phib width is not 2 * layers")
         _check(library().lbm_advance_bounded(self._h, steps, a.ctypes.data, lay), "lbm_advance_bounded")
 
+    def advance_bounded_wave(self, wave: LbmWave, steps: int, layers: int = 0):
+        """Bounded problem: `steps` steps with the outer layers reset from the
+        travelling wave `wave`, evaluated on the device."""
+        _check(library().lbm_advance_bounded_wave(self._h, int(steps), ctypes.byref(wave), int(layers)),
+               "lbm_advance_bounded_wave")
+
+    def wave_rows(self, wave: LbmWave, steps: int, layers: int = 0) -> np.ndarray:
+        """The (steps, 2 layers) boundary rows advance_bounded_wave would use."""
+        lay = int(layers) if layers else self.problem.lattice() // 2
+        out = np.empty((int(steps), 2 * lay), dtype=np.float64)
+        _check(library().lbm_wave_rows(self._h, int(steps), ctypes.byref(wave), lay, out.ctypes.data),
+               "lbm_wave_rows")
+        return out
+
     def read_phi(self, out=None, allow_nonfinite: bool = False) -> np.ndarray:
         if out is not None and hasattr(out, "data_ptr"):
             s = library().lbm_read_phi(self._h, int(out.data_ptr()), 1)
@@ -362,6 +413,17 @@ class Batch:
         ptrs = (ctypes.c_void_p * len(arrs))(*[a.ctypes.data if a is not None else None for a in arrs])
         _check(library().lbm_batch_advance_bounded(self._h, int(steps), ctypes.cast(ptrs, ctypes.c_void_p), int(layers)),
                "lbm_batch_advance_bounded")
+
+    def advance_bounded_wave(self, waves, steps: int, layers: int = 0):
+        """Every instance advances `steps` steps; bounded instance i resets its
+        outer layers from waves[i] (an LbmWave evaluated on the device; None
+        for periodic instances)."""
+        arr = (LbmWave * len(waves))()
+        for i, w in enumerate(waves):
+            if w is not None:
+                arr[i] = w
+        _check(library().lbm_batch_advance_bounded_wave(self._h, int(steps), ctypes.cast(arr, ctypes.c_void_p),
+                                                        int(layers)), "lbm_batch_advance_bounded_wave")
 
     def read_phi(self, i: int):
         """(phi, status) of instance i; status is OK or NONFINITE for that instance."""

@@ -315,6 +315,15 @@ def table8_bounded(tau: float = 0.97, prec: int = F64):
     return p, x, exact
 
 
+def table8_wave() -> dict:
+    """Table VIII's front as a travelling wave phi* = a + b h(z)^p with the
+    logistic h(z) = 1 / (1 + e^z), z = k (x - xc - c t): a = 2 xi, b = -2 xi,
+    p = 2, k = 2 nu, xc = 0, c = xi (the same closed form as table8_bounded)."""
+    ga, de = 9e-4, 2e-5
+    nu, xi = -ga / (10 * de), 6 * ga ** 2 / (25 * de)
+    return dict(shape="logistic", a=2 * xi, b=-2 * xi, p=2.0, k=2 * nu, xc=0.0, c=xi)
+
+
 def power_batch_instance(i: int, prec: int = F64, steps: int = 2000) -> Instance:
     """Real-power batch: phi_t + phi^n phi_x + delta phi_xxx = 0, n = 0.5 or 1.5
     (Bernoulli 1/2), delta ~ U[0.5, 2], N log-uniform [256, 4096] on [-20, 20),

@@ -211,3 +211,13 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         lbm.library()
     with pytest.raises(ImportError):
         lbm.validate(PROBLEMS["kdv"])
+
+
+def test_wave_struct_layout():
+    """lbm_wave: two int32 then ten doubles (88 bytes), as include/lbmhpde.h lays it out."""
+    import ctypes
+    W_ = lbm.LbmWave
+    assert ctypes.sizeof(W_) == 88
+    assert [W_.a.offset, W_.d.offset, W_.k.offset, W_.x_first.offset, W_.t0.offset] == [8, 32, 48, 72, 80]
+    w = lbm.make_wave("logistic", 1.0, -1.0, 2.0, 0.5, 0.0, 0.1, -4.0)
+    assert w.shape == lbm.WAVE_LOGISTIC and w.d == 0.0 and w.r == 0.0
