@@ -6,6 +6,8 @@
 // `layers` right nodes.
 #include "wave.hpp"
 
+#include <cmath>
+
 namespace lbm {
 namespace {
 
@@ -46,7 +48,8 @@ __global__ __launch_bounds__(256) void k_wave_rows(double* __restrict__ rows, in
   rows[idx] = w.a + w.b * wave_power(h, w.p, ip) + w.d * wave_power(h, w.r, ir);
 }
 
-int integer_exponent(double e) { return (e == (double)(int)e && e <= 64.0) ? (int)e : -1; }
+// e itself when it is a whole number <= 64 (bounded before the conversion), else -1
+int integer_exponent(double e) { return (e <= 64.0 && e == std::floor(e)) ? (int)e : -1; }
 
 }  // namespace
 
