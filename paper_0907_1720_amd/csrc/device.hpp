@@ -28,7 +28,8 @@ struct DevCoef {
   float w0f;
   float pad_[3];
   float wHf[8][kRow];        // FP32 relaxation: omega * H[j][d], H = G shifted to the rest state
-  // Equilibria with real (non-integer) powers of phi (variant parity 2):
+  // Equilibria with real (non-integer) powers of phi (variant parity 2, or 3
+  // for the two classes phi^0 and phi^(1/2)):
   //   f_eq_j(phi) = sum_{c < gF} phi^gnu[c] sum_d G[c][j][d] phi^d
   int32_t gF;                // classes; 0 for polynomial equilibria
   int32_t groots;            // 1: every gnu is 1/2, 1/4 or 3/4 (square roots suffice, no log2)
@@ -189,7 +190,7 @@ struct Relaxer {
     w0 = w0_;
     s0 = cf->s0;
     cst = cf->cst;
-    if constexpr (P != 2) {
+    if constexpr (P < 2) {
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
         top[j] = c[j * kRow + K - 1];
@@ -200,7 +201,7 @@ struct Relaxer {
 
   __device__ __forceinline__ void operator()(T (&f)[Q]) const {
     double s = (double)f[0];
-    if constexpr ((kRest && P == 1) || (sizeof(T) == 4 && P == 2)) s = s0 + s;
+    if constexpr ((kRest && P == 1) || (sizeof(T) == 4 && P >= 2)) s = s0 + s;
 #pragma unroll
     for (int j = 1; j < Q; ++j) s += (double)f[j];
     const A p = (A)s;
@@ -242,6 +243,26 @@ struct Relaxer {
       for (int j = 0; j < Q; ++j) {
         const double add = sizeof(T) == 4 ? cst[j] : 0.0;
         f[j] = (T)__builtin_fma((double)w0, (double)f[j], acc[j] + add);
+      }
+    } else if constexpr (P == 3) {
+      // the common two-class case, phi^0 and phi^(1/2) (half-integer exponents):
+      // the parity-2 arithmetic in the same order, without the class loop and
+      // the general powers, so that it fits eight waves per SIMD
+      const DevCoef* __restrict__ g = cfp;
+      const double r = __builtin_sqrt(s);
+      const double w0c = int_pow(s, g->gstep[0]), b0 = int_pow(s, g->gd0[0]);
+      const double w1c = int_pow(s, g->gstep[1]), b1 = r * int_pow(s, g->gd0[1]);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        double a0 = g->gwc[0][j][D], a1 = g->gwc[1][j][D];
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) {
+          a0 = __builtin_fma(a0, w0c, g->gwc[0][j][d]);
+          a1 = __builtin_fma(a1, w1c, g->gwc[1][j][d]);
+        }
+        const double acc = __builtin_fma(b1, a1, b0 * a0);
+        const double add = sizeof(T) == 4 ? cst[j] : 0.0;
+        f[j] = (T)__builtin_fma((double)w0, (double)f[j], acc + add);
       }
     } else if constexpr (P == 0) {
 #pragma unroll

@@ -9,7 +9,8 @@
 // Dense (P = 0): D1Q5 KdV/KS/K(2,2) 5, cubic Pi 13, quartic Pi_1 up to 13;
 // D1Q7 Kawahara 7, cubic Pi 13, quartic Pi_1 19.  Odd (P = 1): mKdV 9.  Power
 // sums with real exponents (P = 2): degree 2, 5, 7 or 11 of each class's
-// polynomial in phi^step (its strided layout).
+// polynomial in phi^step (its strided layout); P = 3: the same for exactly the
+// classes phi^0 and phi^(1/2), degree 2 or 5.
 #define LBM_VARIANT_CASES \
   LBM_CASE(5, 0)          \
   LBM_CASE(7, 0)          \
@@ -23,7 +24,9 @@
   LBM_CASE(2, 2)          \
   LBM_CASE(5, 2)          \
   LBM_CASE(7, 2)          \
-  LBM_CASE(11, 2)
+  LBM_CASE(11, 2)         \
+  LBM_CASE(2, 3)          \
+  LBM_CASE(5, 3)
 
 // dense degrees available to the initialisation kernel
 #define LBM_INIT_CASES \
@@ -41,11 +44,15 @@ inline int padded_degree(int D, int parity) {
   const int dense[] = {5, 7, 9, 13, 19};
   const int odd[] = {5, 9, 13, 19};
   const int power_sum[] = {2, 5, 7, 11};
+  const int half_powers[] = {2, 5};
   if (parity == 0) {
     for (int v : dense)
       if (v >= D) return v;
   } else if (parity == 2) {
     for (int v : power_sum)
+      if (v >= D) return v;
+  } else if (parity == 3) {
+    for (int v : half_powers)
       if (v >= D) return v;
   } else {
     for (int v : odd)

@@ -348,6 +348,7 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
 template <int Q, int D, int P, typename A>
 constexpr int resident_waves_per_simd() {
   if constexpr (P == 2) return 1;
+  if constexpr (P == 3) return 8;
   if constexpr (sizeof(A) == 4) return 8;
   if constexpr (Q <= 5) return (P ? D <= 9 : D <= 5) ? 8 : 1;
   return 1;
@@ -444,7 +445,7 @@ __device__ __forceinline__ void tile_instance(T* __restrict__ S, const T* __rest
   __syncthreads();
   // two nodes per iteration, except for the power sums (whose per-node
   // arithmetic already fills the registers)
-  constexpr int U = P == 2 ? 1 : 2;
+  constexpr int U = P >= 2 ? 1 : 2;
   for (int s = 0; s < steps; ++s) {
     const int lo = s * H, hi = W - s * H;
     if ((s & 1) == 0)

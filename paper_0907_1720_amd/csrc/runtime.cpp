@@ -294,10 +294,15 @@ lbm_status prepare_one(const lbm_desc& d, HostInst* hp) {
   for (int j = 0; j < h.mdl.q && odd; ++j)
     for (int p = 0; p <= h.mdl.D; p += 2)
       if (h.mdl.G[j][p] != 0.0) odd = false;
-  const int parity = h.mdl.gF > 0 ? 2 : (odd ? 1 : 0);
+  int parity = h.mdl.gF > 0 ? 2 : (odd ? 1 : 0);
   int kmax = 1;   // power sums: the longest strided class
   for (int c = 0; c < h.mdl.gF; ++c) kmax = std::max(kmax, h.mdl.gK[c]);
-  const int kd = padded_degree(h.mdl.gF > 0 ? kmax - 1 : h.mdl.D, parity);
+  int kd = padded_degree(h.mdl.gF > 0 ? kmax - 1 : h.mdl.D, parity);
+  // exactly the classes phi^0 and phi^(1/2): the specialised variant, if its degree fits
+  if (parity == 2 && h.mdl.gF == 2 && h.mdl.gnu[1] == 0.5 && padded_degree(kmax - 1, 3) > 0) {
+    parity = 3;
+    kd = padded_degree(kmax - 1, 3);
+  }
   // power sums initialise through their own tables; any init variant serves
   h.Dinit = h.mdl.gF > 0 ? padded_degree(1, 0) : padded_degree(h.mdl.D, 0);
   if (kd == 0 || h.Dinit == 0) return LBM_ERR_UNSUPPORTED;
