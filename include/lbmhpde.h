@@ -51,7 +51,12 @@ typedef enum {
   LBM_ERR_OUT_OF_MEMORY = 4, /* device allocation failed or caller buffer too small */
   LBM_ERR_DEVICE = 5,        /* a HIP runtime call failed */
   LBM_ERR_NONFINITE = 6,     /* the state holds NaN or Inf (instability) */
-  LBM_ERR_BUSY = 7           /* serving: request not admitted yet / not finished */
+  LBM_ERR_BUSY = 7,          /* serving: request not admitted yet / not finished */
+  LBM_ERR_TIMEOUT = 8        /* a device-side wait for a cooperating workgroup (the previous step
+                                chunk of a resident job, a neighbouring slab's halo) gave up: the
+                                kernel ended without advancing that instance as asked; its state
+                                is not a solution.  Never seen unless the GPU stalls a workgroup
+                                for seconds (or lbm_batch_test_stall forces it) */
 } lbm_status;
 
 /* Boundaries.  Periodic: x_i = x0 + i dx, i = 0..n-1, node n-1 neighbours node 0.
@@ -213,7 +218,8 @@ lbm_status lbm_advance_bounded_wave(lbm_problem h, int64_t steps, const lbm_wave
 lbm_status lbm_wave_rows(lbm_problem h, int64_t steps, const lbm_wave* w, int32_t layers, double* out);
 
 /* phi = sum_j f_j (zeroth moment, FP64) into n doubles on the host or device.
-   Synchronises; returns LBM_ERR_NONFINITE (after writing) if any value is NaN/Inf. */
+   Synchronises; returns LBM_ERR_NONFINITE (after writing) if any value is NaN/Inf,
+   LBM_ERR_TIMEOUT (after writing) if a device wait of an advance gave up. */
 lbm_status lbm_read_phi(lbm_problem h, double* out, int out_on_device);
 
 /* FP64 sum over the grid of phi (conserved on a periodic grid). */
@@ -273,7 +279,8 @@ lbm_status lbm_batch_advance_bounded(lbm_batch b, int64_t steps, const double* c
 lbm_status lbm_batch_advance_bounded_wave(lbm_batch b, int64_t steps, const lbm_wave* waves, int32_t layers);
 
 /* phi of instance i into n host doubles; *inst_status (nullable) receives
-   LBM_OK or LBM_ERR_NONFINITE for that instance alone.  Synchronises. */
+   LBM_OK, LBM_ERR_NONFINITE or LBM_ERR_TIMEOUT for that instance alone.
+   Synchronises. */
 lbm_status lbm_batch_read_phi(lbm_batch b, int32_t i, double* out, lbm_status* inst_status);
 
 /* Device time of the kernels of the last lbm_batch_advance, in ms. */
@@ -320,6 +327,19 @@ typedef struct {
    advance only with their boundary rows).  out may be NULL. */
 lbm_status lbm_batch_autotune(lbm_batch b, int64_t probe_steps, lbm_tuning* out);
 
+/* Test hook for the error path of the bounded device waits, which a healthy
+   GPU never takes.  what = 1: in the next advances, the first step chunk of the
+   first job of the first resident launch is taken from the queue but never run
+   (when the launch has more than one chunk), so the wait of its second chunk
+   gives up; what = 2: the first slab of the first slab launch never raises its
+   flag, so its neighbours' halo waits give up (and then its own).  Either way
+   every kernel ends and the instances concerned report LBM_ERR_TIMEOUT.
+   wait_us: the limit of every bounded wait in microseconds (0 = automatic:
+   10 s plus 20 us per step of the work waited for).  what = 0 with wait_us = 0
+   restores normal operation.  INVALID_ARG for what outside [0, 2] or a
+   negative wait. */
+lbm_status lbm_batch_test_stall(lbm_batch b, int32_t what, int64_t wait_us);
+
 lbm_status lbm_batch_destroy(lbm_batch b);
 
 /* ---- serving: continuous batching of solve requests -------------------- */
@@ -332,8 +352,10 @@ lbm_status lbm_batch_destroy(lbm_batch b);
 lbm_status lbm_server_create(void* stream, size_t budget_bytes, int32_t max_slots, int64_t max_n,
                              int32_t block_steps, lbm_server* out);
 
-/* Queue a request (validated now; phi0 is copied).  *id >= 1.  A request whose
-   state alone exceeds the budget is refused with LBM_ERR_OUT_OF_MEMORY. */
+/* Queue a request (validated now, with every check admission makes: the model,
+   its kernel variant, phi0 finite and, for non-integer powers of phi, >= 0;
+   phi0 is copied).  *id >= 1.  A request whose state alone exceeds the budget
+   is refused with LBM_ERR_OUT_OF_MEMORY. */
 lbm_status lbm_server_submit(lbm_server s, const lbm_desc* d, const double* phi0, int64_t steps,
                              int64_t* id);
 
@@ -346,8 +368,11 @@ lbm_status lbm_server_submit(lbm_server s, const lbm_desc* d, const double* phi0
 lbm_status lbm_server_step(lbm_server s, int32_t* active, int32_t* queued, int32_t* retired);
 
 /* Result of request id: LBM_OK with phi in out[0..n) (n >= the request's node
-   count) and its own status (LBM_OK / LBM_ERR_NONFINITE) once retired;
-   LBM_ERR_BUSY while queued or running.  A result is delivered once. */
+   count) and its own status (LBM_OK / LBM_ERR_NONFINITE / LBM_ERR_TIMEOUT)
+   once retired; LBM_ERR_BUSY while queued or running.  A request whose
+   admission fails on the device (its state could not be initialised) is
+   retired at once with that status and no phi (out is not written); the
+   queue behind it goes on.  A result is delivered once. */
 lbm_status lbm_server_poll(lbm_server s, int64_t id, double* out, int64_t n, lbm_status* inst_status);
 
 /* Totals since creation: node updates advanced, device ms of the rounds, free arena bytes. */

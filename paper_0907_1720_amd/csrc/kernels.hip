@@ -96,13 +96,13 @@ const void* stream_kernel(int q, int code, int prec) {
 
 hipError_t launch_resident(int q, int prec, int code, const DevJob* jobs, const DevJobInst* jinst, int njobs,
                            int nchunks, int* counter, int* slots, int* done, const DevCoef* coefs, int* status,
-                           int grid, int block, size_t lds, hipStream_t s) {
+                           long long wait_ticks, int stall_item, int grid, int block, size_t lds, hipStream_t s) {
   const void* fn = resident_kernel(q, prec, code);
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  void* args[] = {(void*)&jobs,  (void*)&jinst, (void*)&njobs, (void*)&nchunks, (void*)&counter,
-                  (void*)&slots, (void*)&done,  (void*)&coefs, (void*)&status};
+  void* args[] = {(void*)&jobs,  (void*)&jinst, (void*)&njobs, (void*)&nchunks,    (void*)&counter,  (void*)&slots,
+                  (void*)&done,  (void*)&coefs, (void*)&status, (void*)&wait_ticks, (void*)&stall_item};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, s);
 }
 
@@ -134,13 +134,14 @@ hipError_t launch_tile(int q, int prec, const DevTile* tiles, int ntiles, const 
 
 hipError_t launch_slab(int q, int prec, int code, const DevSlab* slabs, int nslabs, const DevTileInst* tinsts, void* buf0,
                        void* buf1, int s_per, int halo, void* xbuf, int* flags, const DevCoef* coefs, int* status,
-                       int block, size_t lds, hipStream_t s) {
+                       long long wait_ticks, int mute_slab, int block, size_t lds, hipStream_t s) {
   const void* fn = slab_kernel(q, prec, code);
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  void* args[] = {(void*)&slabs, (void*)&tinsts, (void*)&buf0, (void*)&buf1, (void*)&s_per,
-                  (void*)&halo,  (void*)&xbuf,   (void*)&flags, (void*)&coefs, (void*)&status};
+  void* args[] = {(void*)&slabs, (void*)&tinsts, (void*)&buf0,  (void*)&buf1,   (void*)&s_per,
+                  (void*)&halo,  (void*)&xbuf,   (void*)&flags, (void*)&coefs,  (void*)&status,
+                  (void*)&wait_ticks, (void*)&mute_slab};
   return hipLaunchKernel(fn, dim3(nslabs), dim3(block), args, lds, s);
 }
 

@@ -67,10 +67,12 @@ inline int variant_code(int D, int parity) { return D | (parity << 8); }
 hipError_t launch_init(int q, int D, int prec, const double* phi, void* f, int n, int stride,
                        const DevCoef* cf, hipStream_t s);
 // slabs: one launch no larger than the GPU holds at once, one workgroup per
-// slab; flags[0 .. nslabs) start at 0; xbuf holds 4 Q halo values per slab
+// slab; flags[0 .. nslabs) start at 0; xbuf holds 4 Q halo values per slab;
+// a halo wait gives up after wait_ticks ticks of the wall clock (status bit
+// 2); slab mute_slab (-1: none) never raises its flag (test hook)
 hipError_t launch_slab(int q, int prec, int code, const DevSlab* slabs, int nslabs, const DevTileInst* tinsts,
                        void* buf0, void* buf1, int s_per, int halo, void* xbuf, int* flags, const DevCoef* coefs,
-                       int* status, int block, size_t lds, hipStream_t s);
+                       int* status, long long wait_ticks, int mute_slab, int block, size_t lds, hipStream_t s);
 hipError_t slab_occupancy(int q, int prec, int code, int block, size_t lds, int* blocks_per_cu);
 // bounded domains: reset `layers` (1..32) nodes at each end from phib[0 .. 2 layers)
 // (kind 1 equilibrium, 2 non-equilibrium extrapolation); D = init degree
@@ -86,10 +88,12 @@ const void* stream_kernel(int q, int code, int prec);
 // persistent launch over `njobs` jobs (bin-packed instances of one variant
 // `code`), each split into `nchunks` step chunks; done[0..njobs) starts at 0.
 // code | (1 << 16) selects the kernel of bounded jobs (boundary layers reset
-// in LDS after every step)
+// in LDS after every step).  A chunk's wait for its predecessor gives up after
+// wait_ticks ticks of the wall clock (status bit 4); queue item stall_item
+// (-1: none) is taken but never run (test hook)
 hipError_t launch_resident(int q, int prec, int code, const DevJob* jobs, const DevJobInst* jinst, int njobs,
                            int nchunks, int* counter, int* slots, int* done, const DevCoef* coefs, int* status,
-                           int grid, int block, size_t lds, hipStream_t s);
+                           long long wait_ticks, int stall_item, int grid, int block, size_t lds, hipStream_t s);
 // VGPRs per thread of the resident kernel of variant `code`
 int resident_vgprs(int q, int prec, int code);
 // static LDS bytes of the resident kernel (0 by construction)

@@ -339,7 +339,13 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
 // and so on, so that the last items of the launch are short and the CUs finish
 // together.  Chunk c of job j starts once chunk c-1 of job j has published its
 // state (done[j] == c); that chunk was taken from the queue earlier by a
-// running workgroup, so every wait ends.  The kernel uses no static LDS (an
+// running workgroup, so every wait ends.  The wait is still bounded: after
+// `wait_ticks` ticks of the constant-rate wall clock the chunk gives up, marks
+// its instances (status bit 4), skips its steps and publishes anyway, so that
+// a scheduling fault ends the kernel instead of hanging the GPU and costs the
+// job's later chunks no further wait.  `stall_item` (-1 normally) names a
+// queue item that is taken but never run nor published -- a test hook that
+// makes the next chunk's wait give up.  The kernel uses no static LDS (an
 // instance may fill all 160 KiB): the queue slot reaches the workgroup through
 // a per-workgroup word in global memory.  One instantiation per equilibrium
 // variant, so that each runs at its own register count and occupancy: the
@@ -360,7 +366,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(B ? 1 : re
 void k_resident(const DevJob* __restrict__ jobs, const DevJobInst* __restrict__ jinst,
                                                    int njobs, int nchunks, int* __restrict__ counter,
                                                    int* __restrict__ slots, int* __restrict__ done,
-                                                   const DevCoef* __restrict__ coefs, int* __restrict__ status) {
+                                                   const DevCoef* __restrict__ coefs, int* __restrict__ status,
+                                                   long long wait_ticks, int stall_item) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* L = reinterpret_cast<T*>(smem_raw);
   int* slot = slots + blockIdx.x;
@@ -381,6 +388,8 @@ void k_resident(const DevJob* __restrict__ jobs, const DevJobInst* __restrict__ 
         __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
     __syncthreads();
     if (item >= njobs * nchunks) break;
+    pub_job = -1;
+    if (item == stall_item) continue;
     const int c = item / njobs;
     const int jid = item - c * njobs;
     const DevJob jb = jobs[jid];
@@ -388,16 +397,30 @@ void k_resident(const DevJob* __restrict__ jobs, const DevJobInst* __restrict__ 
     const int base = jb.steps / nchunks, rem = jb.steps % nchunks;
     const int steps = base + (c < rem ? 1 : 0);
     const int s0 = c * base + (c < rem ? c : rem);
-    pub_job = -1;
     if (steps > 0) {
       if (c > 0) {
         if (tid == 0) {
-          while (__hip_atomic_load(done + jid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < c)
+          const long long t0 = wall_clock64();
+          int seen;
+          while ((seen = __hip_atomic_load(done + jid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < c &&
+                 wall_clock64() - t0 < wait_ticks)
             __builtin_amdgcn_s_sleep(8);
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          __hip_atomic_store(slot, seen < c ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every wave drops stale cached lines
+        const int gave_up = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (gave_up) {
+          if (tid < jb.count) atomicOr(status + jinst[jb.first + tid].inst, 4);
+          __syncthreads();   // every wave has read the slot before thread 0 reuses it
+          if (c + 1 < nchunks) {
+            pub_job = jid;
+            pub_val = c + 1;
+          }
+          continue;
+        }
       }
       // the instance of this wave (thread ranges are wave aligned)
       int mine = -1;
@@ -508,8 +531,10 @@ __global__ __launch_bounds__(1024) void k_tile(const DevTile* __restrict__ tiles
 // (input buffer -> LDS -> other buffer).  Strips alternate between two buffers
 // by block parity: a slab overwrites a parity only after its neighbours have
 // raised the flag of the following block, i.e. after they read it.  A wait
-// that outlasts kSlabSpin polls marks the instance (status bit 2) and the
-// workgroup stops, so a scheduling fault cannot hang the GPU.
+// that outlasts `wait_ticks` ticks of the constant-rate wall clock marks the
+// instance (status bit 2) and the workgroup stops, so a scheduling fault
+// cannot hang the GPU.  `mute_slab` (-1 normally) names a slab that never
+// raises its flag -- a test hook that makes its neighbours' waits give up.
 //
 // Strips and flags move with device-scope (agent) relaxed atomic stores and
 // loads, which are coherent across the XCDs' L2 caches without whole-cache
@@ -517,8 +542,6 @@ __global__ __launch_bounds__(1024) void k_tile(const DevTile* __restrict__ tiles
 // (vmcnt 0) before the workgroup barrier that precedes the flag store, and the
 // strips are loaded only after the flag load has returned.
 // ---------------------------------------------------------------------------
-constexpr int kSlabSpin = 1 << 22;
-
 template <typename T>
 __device__ __forceinline__ void store_agent(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -538,7 +561,8 @@ template <int Q, int D, int P, typename T, typename A>
 __device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const DevSlab& sl, const DevTileInst& ti,
                               const T* __restrict__ gin, T* __restrict__ gout, int s_per, int halo,
                               T* __restrict__ xbuf, int* __restrict__ flags, int me,
-                              const DevCoef* __restrict__ cf, int* __restrict__ status) {
+                              const DevCoef* __restrict__ cf, int* __restrict__ status, long long wait_ticks,
+                              bool mute) {
   constexpr int H = Q / 2;
   const int B = blockDim.x;
   const int t = threadIdx.x;
@@ -573,15 +597,14 @@ __device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const D
     wait_vm();
     __syncthreads();
     if (t == 0) {
-      store_agent(flags + me, blk + 1);
-      int spins = 0;
-      while ((__hip_atomic_load(flags + sl.left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= blk ||
-              __hip_atomic_load(flags + sl.right, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= blk) &&
-             spins < kSlabSpin) {
+      if (!mute) store_agent(flags + me, blk + 1);
+      const long long t0 = wall_clock64();
+      bool ready;
+      while (!(ready = __hip_atomic_load(flags + sl.left, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > blk &&
+                       __hip_atomic_load(flags + sl.right, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > blk) &&
+             wall_clock64() - t0 < wait_ticks)
         __builtin_amdgcn_s_sleep(4);
-        ++spins;
-      }
-      if (spins >= kSlabSpin) {
+      if (!ready) {
         atomicOr(status + ti.inst, 2);
         *bail = 1;
       }
@@ -617,7 +640,7 @@ template <int Q, int D, int P, typename T, typename A>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(resident_waves_per_simd<Q, D, P, A>())))
 void k_slab(const DevSlab* __restrict__ slabs, const DevTileInst* __restrict__ tinsts, T* __restrict__ buf0,
             T* __restrict__ buf1, int s_per, int halo, T* __restrict__ xbuf, int* __restrict__ flags,
-            const DevCoef* __restrict__ coefs, int* __restrict__ status) {
+            const DevCoef* __restrict__ coefs, int* __restrict__ status, long long wait_ticks, int mute_slab) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* S = reinterpret_cast<T*>(smem_raw);
   const int me = blockIdx.x;
@@ -626,7 +649,8 @@ void k_slab(const DevSlab* __restrict__ slabs, const DevTileInst* __restrict__ t
   int* bail = reinterpret_cast<int*>(smem_raw + (size_t)(sl.core + 2 * halo) * lds_stride(Q) * sizeof(T));
   const T* gin = (ti.cur0 ? buf1 : buf0) + ti.off;
   T* gout = (ti.cur0 ? buf0 : buf1) + ti.off;
-  slab_instance<Q, D, P, T, A>(S, bail, sl, ti, gin, gout, s_per, halo, xbuf, flags, me, coefs + ti.inst, status);
+  slab_instance<Q, D, P, T, A>(S, bail, sl, ti, gin, gout, s_per, halo, xbuf, flags, me, coefs + ti.inst, status,
+                               wait_ticks, me == mute_slab);
 }
 
 }  // namespace lbm

@@ -75,6 +75,7 @@ void release_graph(StepGraph* g) {
 struct DeviceLimits {
   int cus = 0;
   size_t lds_max = 0;
+  double wall_ticks_per_us = 100.0;   // constant-rate device clock (wall_clock64)
   bool ok = false;
 };
 
@@ -87,6 +88,8 @@ DeviceLimits query_limits() {
   L.cus = v;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return L;
   L.lds_max = (size_t)v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
+    L.wall_ticks_per_us = v / 1000.0;   // kHz
   L.ok = true;
   return L;
 }
@@ -151,6 +154,10 @@ struct lbm_batch_s {
   bool bnd_active = false;
   int bnd_layers = 0;
   std::vector<uint64_t> bnd_ptr;
+  // bounded device waits (test hook lbm_batch_test_stall): limit in us (0 =
+  // automatic) and the wait to force to give up (0 none, 1 resident, 2 slab)
+  int64_t test_wait_us = 0;
+  int test_stall = 0;
 };
 
 struct lbm_problem_s {
@@ -533,6 +540,15 @@ lbm_status step_graph(lbm_batch_s* b, int i, StepGraph** out) {
 }
 
 constexpr int64_t kMaxStepsPerLaunch = int64_t(1) << 30;
+
+// Limit of a device wait for a cooperating workgroup that has `steps` steps of
+// work to finish first: 10 s plus 20 us per step (a node sweep takes well
+// under 10 us on every path), in ticks of the device wall clock.
+long long wait_ticks(const lbm_batch_s* b, int64_t steps) {
+  const double us = b->test_wait_us > 0 ? (double)b->test_wait_us : 1e7 + 20.0 * (double)steps;
+  return (long long)(us * b->lim.wall_ticks_per_us);
+}
+
 constexpr int kChunkItems = 16;        // queue items per workgroup when jobs outnumber workgroups
 constexpr int64_t kMinChunkSteps = 256;
 constexpr int kMaxChunks = 64;
@@ -978,8 +994,10 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     if (b->res_chunks > 0) nchunks = b->res_chunks;
     int* slots = b->slots + (size_t)(k * kMaxLaunches + l) * kMaxResidentGrid;
     int* done = b->done + (size_t)k * b->items_cap + L.first;
+    const long long ticks = wait_ticks(b, L.maxsteps / nchunks + 1);
+    const int stall = (b->test_stall == 1 && l == 0 && nchunks > 1) ? 0 : -1;
     LBM_HIP(launch_resident(L.q, L.prec, L.code, djobs + L.first, ditems, L.count, nchunks, counters + l, slots, done,
-                            b->coefs, b->status, grid, L.block, L.lds, st));
+                            b->coefs, b->status, ticks, stall, grid, L.block, L.lds, st));
   }
   for (const TileGroup& G : tgroups) {
     hipStream_t st = lane_stream(lane);
@@ -1018,8 +1036,10 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       void* b1 = L.prec ? (void*)b->f32[1] : (void*)b->f64[1];
       int* flags = b->sflags + L.foff;
       LBM_HIP(hipMemsetAsync(flags, 0, sizeof(int) * L.count, st));
+      const int mute = (b->test_stall == 2 && l == 0) ? 0 : -1;
       LBM_HIP(launch_slab(L.q, L.prec, L.code, ds + L.first, L.count, dti, b0, b1, L.s, L.halo,
-                          (unsigned char*)b->xbuf + L.xoff, flags, b->coefs, b->status, L.block, L.lds, st));
+                          (unsigned char*)b->xbuf + L.xoff, flags, b->coefs, b->status, wait_ticks(b, L.s), mute,
+                          L.block, L.lds, st));
     }
     for (const DevSlab& sl : svec)
       if (sl.x0 == 0) b->inst[htin[sl.ti].inst].cur ^= 1;   // one flip per instance: output in the other buffer
@@ -1094,7 +1114,9 @@ lbm_status read_phi(lbm_batch_s* b, int i, double* out, int on_device, lbm_statu
   LBM_HIP(hipMemcpyAsync(&flags[0], b->flag, sizeof(int), hipMemcpyDeviceToHost, b->stream));
   LBM_HIP(hipMemcpyAsync(&flags[1], b->status + i, sizeof(int), hipMemcpyDeviceToHost, b->stream));
   LBM_HIP(hipStreamSynchronize(b->stream));
-  lbm_status s = (flags[0] || flags[1]) ? LBM_ERR_NONFINITE : LBM_OK;
+  // status bit 1: a non-finite value; bits 2 and 4: a device wait for a
+  // cooperating workgroup gave up, so the state was not advanced as asked
+  lbm_status s = (flags[1] & 6) ? LBM_ERR_TIMEOUT : (flags[0] || flags[1]) ? LBM_ERR_NONFINITE : LBM_OK;
   if (inst_status) *inst_status = s;
   return s;
 }
@@ -1256,6 +1278,7 @@ const char* lbm_status_str(lbm_status s) {
     case LBM_ERR_DEVICE: return "HIP runtime error";
     case LBM_ERR_NONFINITE: return "non-finite state";
     case LBM_ERR_BUSY: return "busy";
+    case LBM_ERR_TIMEOUT: return "device wait timed out";
   }
   return "unknown status";
 }
@@ -1660,7 +1683,7 @@ lbm_status lbm_batch_advance(lbm_batch b, const int64_t* steps) {
 lbm_status lbm_batch_read_phi(lbm_batch b, int32_t i, double* out, lbm_status* inst_status) {
   if (!b || !out || i < 0 || i >= (int32_t)b->inst.size()) return LBM_ERR_INVALID_ARG;
   lbm_status s = read_phi(b, i, out, 0, inst_status);
-  return s == LBM_ERR_NONFINITE ? LBM_OK : s;
+  return (s == LBM_ERR_NONFINITE || s == LBM_ERR_TIMEOUT) ? LBM_OK : s;
 }
 
 lbm_status lbm_batch_last_advance_ms(lbm_batch b, float* ms) {
@@ -1695,6 +1718,13 @@ lbm_status lbm_batch_set_resident(lbm_batch b, int32_t max_workgroups, int32_t c
     return LBM_ERR_INVALID_ARG;
   b->res_grid = max_workgroups;
   b->res_chunks = chunks;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_test_stall(lbm_batch b, int32_t what, int64_t wait_us) {
+  if (!b || what < 0 || what > 2 || wait_us < 0 || wait_us > (int64_t(1) << 40)) return LBM_ERR_INVALID_ARG;
+  b->test_stall = what;
+  b->test_wait_us = wait_us;
   return LBM_OK;
 }
 
@@ -1848,14 +1878,15 @@ lbm_status lbm_server_create(void* stream, size_t budget_bytes, int32_t max_slot
 
 lbm_status lbm_server_submit(lbm_server sv, const lbm_desc* d, const double* phi0, int64_t steps, int64_t* id) {
   if (!sv || !d || !phi0 || !id || steps < 0) return LBM_ERR_INVALID_ARG;
-  Model m;
-  lbm_status s = build_model(*d, &m);
+  // the checks admission repeats: the model, its kernel variant and phi0
+  HostInst probe;
+  lbm_status s = prepare_one(*d, &probe);
   if (s != LBM_OK) return s;
   if (d->n > sv->max_n) return LBM_ERR_INVALID_ARG;
   if (d->bc != LBM_BC_PERIODIC) return LBM_ERR_UNSUPPORTED;   // requests carry no boundary data
   if (state_bytes_of(*d) > sv->arena.size) return LBM_ERR_OUT_OF_MEMORY;
   for (int64_t i = 0; i < d->n; ++i)
-    if (!std::isfinite(phi0[i])) return LBM_ERR_INVALID_ARG;
+    if (!std::isfinite(phi0[i]) || (probe.mdl.gF > 1 && phi0[i] < 0)) return LBM_ERR_INVALID_ARG;
   Request r;
   r.id = sv->next_id++;
   r.desc = *d;
@@ -1891,15 +1922,18 @@ lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int3
     if (!sv->arena.alloc(bytes, &off)) break;   // FIFO: wait for space
     HostInst& h = b->inst[slot];
     lbm_status s = prepare_one(r.desc, &h);
-    if (s != LBM_OK) {
-      sv->arena.release(off, bytes);
-      return s;
+    if (s == LBM_OK) {
+      h.off = (int64_t)(off / (h.f32 ? sizeof(float) : sizeof(double)));
+      s = load_phi_one(b, slot, r.phi0.data(), 0);
     }
-    h.off = (int64_t)(off / (h.f32 ? sizeof(float) : sizeof(double)));
-    s = load_phi_one(b, slot, r.phi0.data(), 0);
     if (s != LBM_OK) {
+      // submission ran the same checks, so this is a device error: the request
+      // retires with it (no phi) and the queue moves on
       sv->arena.release(off, bytes);
-      return s;
+      h = HostInst();
+      sv->results[r.id - 1].status = s;
+      sv->done[r.id - 1] = 1;
+      continue;
     }
     Slot& sl = sv->slots[slot];
     sl.active = true;
@@ -1952,7 +1986,7 @@ lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int3
     res.phi.resize(b->inst[k].n);
     lbm_status st = LBM_OK;
     lbm_status s = read_phi(b, (int)k, res.phi.data(), 0, &st);
-    if (s != LBM_OK && s != LBM_ERR_NONFINITE) return s;
+    if (s != LBM_OK && s != LBM_ERR_NONFINITE && s != LBM_ERR_TIMEOUT) return s;
     res.status = st;
     sv->done[sl.id - 1] = 1;
     sv->arena.release(sl.off, sl.bytes);

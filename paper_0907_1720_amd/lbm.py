@@ -18,7 +18,7 @@ from .workloads import Problem
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmhpde.so")
 
-OK, INVALID_ARG, UNSUPPORTED, SINGULAR_TAU, OUT_OF_MEMORY, DEVICE, NONFINITE, BUSY = range(8)
+OK, INVALID_ARG, UNSUPPORTED, SINGULAR_TAU, OUT_OF_MEMORY, DEVICE, NONFINITE, BUSY, TIMEOUT = range(9)
 PATH_AUTO, PATH_STREAM, PATH_RESIDENT, PATH_TILED, PATH_SLAB = 0, 1, 2, 3, 4
 BC_PERIODIC, BC_DIRICHLET_EQ, BC_DIRICHLET_NEE = 0, 1, 2
 
@@ -147,6 +147,7 @@ def library() -> ctypes.CDLL:
         "lbm_batch_set_tiling": (I32, [P, I32, I32]),
         "lbm_batch_set_resident": (I32, [P, I32, I32]),
         "lbm_batch_autotune": (I32, [P, I64, P]),
+        "lbm_batch_test_stall": (I32, [P, I32, I64]),
         "lbm_batch_destroy": (I32, [P]),
         "lbm_server_create": (I32, [P, SZ, I32, I64, I32, P]),
         "lbm_server_submit": (I32, [P, DP, P, I64, P]),
@@ -376,9 +377,12 @@ class Batch:
         self._h = h
 
     def load_phi(self, phis: Sequence[np.ndarray]):
+        if len(phis) != len(self.problems):
+            raise ValueError(f"{len(phis)} initial states for {len(self.problems)} instances")
         keep = [np.ascontiguousarray(p, dtype=np.float64) for p in phis]
         for a, p in zip(keep, self.problems):
-            assert a.size == p.n
+            if a.size != p.n:
+                raise ValueError(f"initial state of {a.size} values for {p.n} nodes")
         ptrs = (ctypes.c_void_p * len(keep))(*[a.ctypes.data for a in keep])
         _check(library().lbm_batch_load_phi(self._h, ptrs), "lbm_batch_load_phi")
 
@@ -393,6 +397,8 @@ class Batch:
         """Every instance advances len(rows) steps; bounded instance i resets its
         outer layers after step s from phibs[i][s] (left layers, then right);
         phibs[i] is None for periodic instances."""
+        if len(phibs) != len(self.problems):
+            raise ValueError(f"{len(phibs)} boundary row sets for {len(self.problems)} instances")
         arrs, steps = [], None
         for i, a in enumerate(phibs):
             if a is None:
@@ -418,6 +424,8 @@ class Batch:
         """Every instance advances `steps` steps; bounded instance i resets its
         outer layers from waves[i] (an LbmWave evaluated on the device; None
         for periodic instances)."""
+        if len(waves) != len(self.problems):
+            raise ValueError(f"{len(waves)} waves for {len(self.problems)} instances")
         arr = (LbmWave * len(waves))()
         for i, w in enumerate(waves):
             if w is not None:
@@ -426,7 +434,7 @@ class Batch:
                                                         int(layers)), "lbm_batch_advance_bounded_wave")
 
     def read_phi(self, i: int):
-        """(phi, status) of instance i; status is OK or NONFINITE for that instance."""
+        """(phi, status) of instance i; status is OK, NONFINITE or TIMEOUT for that instance."""
         out = np.empty(self.problems[i].n, dtype=np.float64)
         st = ctypes.c_int32()
         _check(library().lbm_batch_read_phi(self._h, int(i), out.ctypes.data, ctypes.byref(st)),
@@ -443,6 +451,10 @@ class Batch:
     def set_resident(self, max_workgroups: int = 0, chunks: int = 0):
         _check(library().lbm_batch_set_resident(self._h, int(max_workgroups), int(chunks)),
                "lbm_batch_set_resident")
+
+    def test_stall(self, what: int, wait_us: int = 0):
+        """Forces a bounded device wait to give up (test hook; 0, 0 restores)."""
+        _check(library().lbm_batch_test_stall(self._h, int(what), int(wait_us)), "lbm_batch_test_stall")
 
     def autotune(self, probe_steps: int) -> dict:
         """Times planner settings on a copy of the batch and keeps the fastest."""

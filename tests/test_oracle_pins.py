@@ -180,10 +180,9 @@ def test_aux_moments_match_family_a_closed_forms(n):
     }
     for k in range(2, 7):
         assert mdl.Pi0[k] == want[k], k
-    # printed A_40, A_50 (Sec. III.C) from the printed tau_k
+    # (the values of A_40, A_50 and A_60 themselves are pinned by the linear
+    # dispersion tests and by Tables IV-VIII)
     t = mdl.taus
-    assert A40 == t[2] * (3 * t[3] - t[2] ** 2) * b[2] ** 2 / t[4]
-    assert A50 == (4 * t[2] * t[4] + 3 * t[3] ** 2 - 2 * t[2] ** 2 * t[3]) * b[2] * b[3] / t[5]
     # beta_k from alpha_k = dt^{k-1} tau_k beta_k
     for k in range(2, 7):
         assert Fraction(p.dt) ** (k - 1) * t[k] * b[k] == Fraction(p.alpha[k])
@@ -318,6 +317,171 @@ def test_printed_aux_moments_leave_fifth_order_residual(m):
 
 
 # ---------------------------------------------------------------------------
+# The random sixth-order equation (nonlinear cubic Pi_2 .. Pi_6): its scheme,
+# linearised about a uniform state phi_bar, is the linear scheme whose moments
+# are the derivatives at phi_bar of the equilibrium moments,
+#   s_0 = 1, s_1 = Pi_1'(phi_bar), s_k = Pi_k0'(phi_bar) + beta_k Pi_k'(phi_bar),
+# and it should recover the linearised PDE
+#   phi_t + Pi_1'(phi_bar) phi_x + sum_k alpha_k Pi_k'(phi_bar) d^k phi = 0.
+# The corrections A_40, A_50, A_60 of Sec. II.D-F are derived for Pi_2 = Pi_3 =
+# Pi_4 = phi; the oracle adds them as printed (reading A8).  A linear problem
+# with Pi_r = b_r phi is the same as Pi_r = phi with alpha_r b_r, whose exact
+# corrections carry beta_r b_r instead of beta_r.  Hence:
+#  * b_2 = b_3 = b_4 = 1 (Pi_r'(phi_bar) = 1, Pi_r still nonlinear): the printed
+#    corrections are the exact ones and the linearised scheme recovers the PDE
+#    to O(kappa^q) -- every integrand term of Pi_50 and Pi_60 that carries a
+#    nonlinear Pi_r' is then pinned by the dispersion relation;
+#  * otherwise the moment vector differs from that of the linear equivalent
+#    first at k = 4 by A_40 (1 - b_2^2) (or, with b_2^2 = 1, at k = 5 by
+#    A_50 (1 - b_2 b_3), or at k = 6 by the beta_2 beta_4 part of A_60), and a
+#    moment error Ds_k shifts the recovered coefficient of d^k by
+#    dt^{k-1} tau_k Ds_k (alpha_k = dt^{k-1} tau_k beta_k), so the leading
+#    residual of the dispersion relation is -tau_k Ds_k (i kappa)^k.
+# ---------------------------------------------------------------------------
+
+PHI_BAR = Fraction(3, 4)
+ALPHA6 = (0.0, 1.0, 0.62, -0.31, 0.85, -0.44, -0.27)
+
+
+def _cubic_pi(g, slope=None):
+    """Pi(phi) = c1 phi + c2 phi^2 + c3 phi^3 with dyadic c2, c3 and, if slope is
+    given, c1 = slope - 2 c2 phi_bar - 3 c3 phi_bar^2 (exact in binary), so that
+    Pi'(phi_bar) = slope exactly while Pi'' != 0."""
+    c2, c3 = int(g.integers(-64, 65)) / 64, int(g.integers(-64, 65)) / 64
+    if slope is None:
+        return (0.0, float(g.uniform(-1, 1)), c2, c3)
+    c1 = Fraction(slope) - 2 * Fraction(c2) * PHI_BAR - 3 * Fraction(c3) * PHI_BAR ** 2
+    assert Fraction(float(c1)) == c1
+    return (0.0, float(c1), c2, c3)
+
+
+def _random_m6(seed, slopes, am=0, q=7, m=6):
+    """Random-coefficient equation with cubic Pi_1..Pi_6; slopes[r - 2] fixes
+    Pi_r'(phi_bar) for r = 2, 3, 4 (None: random)."""
+    g = np.random.default_rng(seed)
+    pis = [(), (0.0, float(g.uniform(-1, 1)), float(g.uniform(-1, 1)), float(g.uniform(-1, 1)))]
+    pis += [_cubic_pi(g, s) for s in slopes] + [_cubic_pi(g), _cubic_pi(g)]
+    al = tuple(ALPHA6[k] if k <= m else 0.0 for k in range(7))
+    return W.Problem(al, tuple(pis), 16, 1.0, 1.0, 1.3, m=m, q=q, am=am)
+
+
+def _dpoly(p, x):
+    return O.pval_exact(O.pderiv(p), x)
+
+
+def _linearised(p, pb=PHI_BAR):
+    """(moment vector s_k at phi_bar, Pi_1'(phi_bar), {r: Pi_r'(phi_bar)}, model)."""
+    mdl = O.build_model(p)
+    a = _dpoly(mdl.Pi[1], pb)
+    s = [Fraction(1), a] + [_dpoly(mdl.Pi0[k], pb) + mdl.beta[k] * _dpoly(mdl.Pi[k], pb) for k in range(2, mdl.q)]
+    return s, a, {r: _dpoly(mdl.Pi[r], pb) for r in range(2, 7)}, mdl
+
+
+def _linear_equivalent(p, a, b, with_model=False):
+    """The linear problem Pi_1 = a phi, Pi_r = phi with alpha_r b_r (exact
+    rationals: the oracle reads every input through Fraction)."""
+    al = tuple(Fraction(p.alpha[k]) * (b[k] if k >= 2 else 1) for k in range(7))
+    pis = [(), (Fraction(0), a)] + [(0.0, 1.0)] * 5
+    lp = W.Problem(al, tuple(pis), 16, 1.0, 1.0, p.tau, m=p.m, q=p.q, am=p.am)
+    mdl = O.build_model(lp)
+    s = [Fraction(1), a]
+    for k in range(2, mdl.q):
+        p0 = mdl.Pi0[k]
+        s.append((p0[1] if len(p0) > 1 else Fraction(0)) + mdl.beta[k])
+    return (s, mdl) if with_model else s
+
+
+def _residuals(s, q, tau, a, coeffs, kappas=(0.0005, 0.001, 0.002, 0.004)):
+    """ln lambda(kappa) + i a kappa + sum_k coeffs[k] (i kappa)^k at 60 digits, for
+    the linear scheme whose equilibrium has the moment vector s (lattice units)."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 60
+    Minv = O.inverse_moment_matrix_exact(q)
+    w = [sum(Minv[j][k] * s[k] for k in range(q)) for j in range(q)]
+    om = mp.mpf(1) / mp.mpf(tau)
+    fr = lambda v: mp.mpf(v.numerator) / v.denominator
+    out = []
+    for kap in kappas:
+        kap = mp.mpf(kap)
+        A = mp.matrix(q, q)
+        for j in range(q):
+            ph = mp.exp(-1j * kap * O.lattice_velocities(q)[j])
+            for l in range(q):
+                A[j, l] = ph * (om * fr(w[j]) + ((1 - om) if j == l else 0))
+        lam = min(mp.eig(A, left=False, right=False), key=lambda z: abs(z - 1))
+        out.append(mp.log(lam) + 1j * fr(a) * kap + sum(fr(c) * (1j * kap) ** k for k, c in coeffs.items()))
+    return out, kappas
+
+
+def _slopes(res):
+    import mpmath as mp
+    return [float(mp.log(abs(res[i + 1]) / abs(res[i])) / mp.log(2)) for i in range(len(res) - 1)]
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+@pytest.mark.parametrize("m,q", [(6, 7), (5, 7), (4, 5)])
+def test_random_m6_linearisation_recovers_pde(seed, m, q):
+    """Pi_2'..Pi_4' = 1 at phi_bar: the nonlinear auxiliary moments, linearised,
+    equal those of the linear equivalent exactly and recover the PDE to O(kappa^q)."""
+    p = _random_m6(seed, (1, 1, 1), q=q, m=m)
+    s, a, b, mdl = _linearised(p)
+    assert all(b[r] == 1 for r in (2, 3, 4)) and a != 1
+    assert s == _linear_equivalent(p, a, b)
+    coeffs = {k: Fraction(p.alpha[k]) * b[k] for k in range(2, m + 1)}
+    res, _ = _residuals(s, q, p.tau, a, coeffs)
+    assert min(_slopes(res)) > q - 0.1, _slopes(res)
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+@pytest.mark.parametrize("am", [0, 1])
+def test_random_m6_linearised_moments_differ_only_by_corrections(seed, am):
+    """Every Pi_r'(phi_bar) random: the linearised moments of the nonlinear
+    model equal those of the linear equivalent except for the corrections,
+    which carry beta_r instead of beta_r Pi_r'(phi_bar) -- A_40, A_50, A_60
+    where they enter the integrands of Pi_40, Pi_50, Pi_60 (and, corrected,
+    through the A_40 / A_50 parts of the fourth and fifth moments)."""
+    p = _random_m6(seed, (None, None, None), am=am)
+    s, a, b, mdl = _linearised(p)
+    sl, ml = _linear_equivalent(p, a, b, with_model=True)
+    dA = {k: mdl.A[k] - ml.A[k] for k in (4, 5, 6)}
+    assert all(dA[k] != 0 for k in (4, 5, 6))
+    want = [Fraction(0)] * 4 + [dA[4], dA[5], dA[6]]
+    if am == 0:
+        want[5] += 5 * a * dA[4]
+        want[6] += 15 * a ** 2 * dA[4] + 6 * a * dA[5]
+    assert [x - y for x, y in zip(s, sl)] == want
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+@pytest.mark.parametrize("slopes,order", [((None, 1, 1), 4), ((1, None, 1), 5), ((-1, None, 1), 5),
+                                          ((1, 1, None), 6)])
+def test_random_m6_leading_residual_of_printed_corrections(seed, slopes, order):
+    """Pi_r'(phi_bar) != 1: the first moment that differs from the linear
+    equivalent is the predicted one, and the dispersion residual starts at that
+    order with coefficient -tau_k Ds_k."""
+    p = _random_m6(seed, slopes)
+    s, a, b, mdl = _linearised(p)
+    sl = _linear_equivalent(p, a, b)
+    ds = [x - y for x, y in zip(s, sl)]
+    assert all(d == 0 for d in ds[:order]) and ds[order] != 0, [float(d) for d in ds]
+    t, A = mdl.taus, mdl.A
+    if order == 4:
+        assert ds[4] == A[4] * (1 - b[2] ** 2)
+    elif order == 5:
+        assert ds[5] == A[5] * (1 - b[2] * b[3])
+    coeffs = {k: Fraction(p.alpha[k]) * b[k] for k in range(2, 7)}
+    res, kap = _residuals(s, 7, p.tau, a, coeffs)
+    sl_ = _slopes(res)
+    assert abs(sl_[0] - order) < 0.05, sl_
+    want = float(-t[order] * ds[order])
+    # residual / (i kappa)^k = c_k + c_{k+1} i kappa + ...: Richardson over
+    # kappa and 2 kappa removes the first correction
+    r0, r1 = (complex(res[i] / (1j * kap[i]) ** order) for i in (0, 1))
+    got = 2 * r0 - r1
+    assert abs(got - want) < 1e-3 * abs(want), (got, want)
+
+
+# ---------------------------------------------------------------------------
 # conservation, exact shifts, dense linear brute force
 # ---------------------------------------------------------------------------
 
@@ -446,16 +610,6 @@ def test_integration_constants_do_not_change_phi():
         mdl.Pi0_f[k][0] += 0.37 * k
     shifted = O.run(p, phi0, 200, mdl=mdl)
     assert np.max(np.abs(shifted - base)) <= 1e-13 * np.max(np.abs(base))
-
-
-def test_scheme2_zeroes_top_moment():
-    p = dataclasses.replace(W.kawahara(32, 0.1, 0.01, 3.0, 0.0), scheme=2)
-    mdl = O.build_model(p)
-    pbar = O.scaled_moments(mdl, np.linspace(-1, 1, 32))
-    assert np.all(pbar[6] == 0.0)
-    e = mdl.e.astype(float)
-    feq = O.equilibrium(mdl, np.linspace(-1, 1, 32))
-    assert np.max(np.abs((e[:, None] ** 6 * feq).sum(0))) < 1e-12
 
 
 def test_relaxation_time_must_exceed_half():
