@@ -170,6 +170,26 @@ lbm_status lbm_load_phi(lbm_problem h, const double* phi, int phi_on_device);
    INVALID_ARG for a bounded problem (those advance with lbm_advance_bounded). */
 lbm_status lbm_advance(lbm_problem h, int64_t steps);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+   harnesses that forbid hipMalloc): lbm_create + lbm_load_phi + lbm_advance +
+   lbm_read_phi of one periodic problem in one call that allocates nothing.
+   phi0 and phi are caller-owned device arrays of d->n doubles (they may be the
+   same array); f := f_eq(phi0), `steps` steps on the LDS-resident path, phi :=
+   sum_j f_j -- the kernels of lbm_advance, so the result is bitwise the one of
+   the handle calls.  Every device buffer besides phi0 and phi (coefficient and
+   job tables, queue words, status flags, the state) lies in one fixed array of
+   272 KiB per GPU, allocated with the library's code object and held until the
+   process ends.  Limits: the state must fit one workgroup's LDS and 256 KiB
+   (d->n <= 8192; e.g. at most 4096 nodes for FP64 D1Q5, 2925 for FP64 D1Q7,
+   8192 for FP32 D1Q5, 5851 for FP32 D1Q7), else LBM_ERR_INVALID_ARG before any
+   device work.  Calls that overlap on one GPU (other streams, other host
+   threads) share that array and race; calls on one stream are ordered.  The
+   array keeps the last call's contents; each call clears what must start at
+   zero.  Synchronises the stream; returns LBM_ERR_NONFINITE if phi holds
+   NaN/Inf, LBM_ERR_INVALID_ARG for a bounded problem, a non-finite phi0 or, with
+   non-integer powers of phi, a negative one. */
+lbm_status lbm_advance_noalloc(const lbm_desc* d, const double* phi0, int64_t steps, double* phi, void* stream);
+
 /* Bounded problems (bc = LBM_BC_DIRICHLET_EQ or _NEE; Sec. IV): advance `steps`
    steps; after step s (s = 1..steps) the `layers` outer nodes at each end are
    reset from the exact solution phib[(s-1) * 2 layers + k]: k < layers holds

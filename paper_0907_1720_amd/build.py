@@ -54,7 +54,7 @@ def build(verbose: bool = False) -> str:
     for src in ("coeffs.cpp", "runtime.cpp"):
         obj = os.path.join(BUILD, src + ".o")
         steps.append((obj, [CLANG] + HOST_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj]))
-    for src in ("kernels.hip", "kernels_wave.hip"):
+    for src in ("kernels.hip", "kernels_wave.hip", "noalloc.hip"):
         obj = os.path.join(BUILD, src + ".o")
         steps.append((obj, [HIPCC] + DEVICE_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj]))
     for q in LATTICES:

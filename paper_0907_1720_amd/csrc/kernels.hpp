@@ -102,6 +102,14 @@ hipError_t launch_phi(int prec, const void* f, double* phi, int n, int stride, i
                       int* nonfinite, hipStream_t s);
 hipError_t launch_sum(const double* v, int n, double* part, int nparts, hipStream_t s);
 hipError_t resident_occupancy(int q, int prec, int code, int block, size_t lds, int* blocks_per_cu);
+// lbm_advance_noalloc: the fixed per-device scratch (tables at offset 0, the
+// state from kNoAllocTableBytes on) and its device address on the current
+// device (looked up once per device); a fill kernel that zeroes n ints
+constexpr size_t kNoAllocTableBytes = size_t(16) << 10;
+constexpr size_t kNoAllocStateBytes = size_t(256) << 10;
+constexpr size_t kNoAllocScratchBytes = kNoAllocTableBytes + kNoAllocStateBytes;
+hipError_t noalloc_scratch(void** out);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 // temporal blocking: launch `launch` of an advance, s_per steps per launch
 hipError_t launch_tile(int q, int prec, const DevTile* tiles, int ntiles, const DevTileInst* tinsts, void* buf0,
                        void* buf1, int launch, int s_per, int halo, const DevCoef* coefs, int* status, int block,

@@ -540,6 +540,7 @@ lbm_status step_graph(lbm_batch_s* b, int i, StepGraph** out) {
 }
 
 constexpr int64_t kMaxStepsPerLaunch = int64_t(1) << 30;
+constexpr int kNoAllocMaxNodes = 8192;   // lbm_advance_noalloc: the largest grid one LDS holds
 
 // Limit of a device wait for a cooperating workgroup that has `steps` steps of
 // work to finish first: 10 s plus 20 us per step (a node sweep takes well
@@ -1374,6 +1375,77 @@ lbm_status lbm_load_phi(lbm_problem h, const double* phi, int phi_on_device) {
 lbm_status lbm_advance(lbm_problem h, int64_t steps) {
   if (!h || steps < 0) return LBM_ERR_INVALID_ARG;
   return advance(h->b, &steps);
+}
+
+// lbm_create + lbm_load_phi + lbm_advance + lbm_read_phi of one periodic
+// problem whose state fits one workgroup's LDS, with every device buffer in
+// the fixed per-device scratch (noalloc.hip): the same kernels (k_init, one
+// resident launch per 2^30 steps, k_phi), so the result is bitwise that of the
+// handle path.  Host-side buffers live on this call's stack.
+lbm_status lbm_advance_noalloc(const lbm_desc* d, const double* phi0, int64_t steps, double* phi, void* stream) {
+  if (!d || !phi0 || !phi || steps < 0 || d->n < 1 || d->n > kNoAllocMaxNodes) return LBM_ERR_INVALID_ARG;
+  if (d->bc != LBM_BC_PERIODIC) return LBM_ERR_INVALID_ARG;
+  const hipStream_t st = (hipStream_t)stream;
+  HostInst h;
+  lbm_status s = prepare_one(*d, &h);
+  if (s != LBM_OK) return s;
+  const DeviceLimits lim = query_limits();
+  if (!lim.ok) return LBM_ERR_DEVICE;
+  const size_t es = elem_size(h);
+  const size_t lds = ((size_t)lds_stride(h.q) * h.n * es + 15) / 16 * 16;
+  if ((size_t)h.q * h.stride * es > kNoAllocStateBytes || lds + resident_static_lds(h.q, h.prec, h.D) > lim.lds_max)
+    return LBM_ERR_INVALID_ARG;
+  void* base = nullptr;
+  LBM_HIP(noalloc_scratch(&base));
+  // tables at the start of the scratch, the state after them
+  static_assert(sizeof(DevCoef) <= 12288, "coefficient table outgrew its scratch region");
+  unsigned char* bytes = (unsigned char*)base;
+  DevCoef* dcoef = (DevCoef*)bytes;
+  DevJob* djob = (DevJob*)(bytes + 12288);
+  DevJobInst* dji = (DevJobInst*)(bytes + 12288 + 256);
+  int* ints = (int*)(bytes + 12288 + 512);   // queue counter, slot, done, status, non-finite flag
+  void* f = bytes + kNoAllocTableBytes;
+  // phi0 on the host: the checks of lbm_load_phi and the rest state (mean of phi0)
+  double host[kNoAllocMaxNodes];
+  LBM_HIP(hipMemcpyAsync(host, phi0, sizeof(double) * h.n, hipMemcpyDeviceToHost, st));
+  LBM_HIP(hipStreamSynchronize(st));
+  long double sum = 0;
+  for (int i = 0; i < h.n; ++i) {
+    if (!std::isfinite(host[i]) || (h.mdl.gF > 1 && host[i] < 0)) return LBM_ERR_INVALID_ARG;
+    sum += host[i];
+  }
+  if (h.f32) set_rest_state(&h.mdl, (double)(sum / h.n));
+  DevCoef cf;
+  fill_devcoef(h, &cf);
+  // one job of one instance: a wave per 64 nodes, at most 16
+  const int waves = std::max(1, std::min(16, (h.n + 63) / 64));
+  DevJob jb{0, 1, 0, h.D, 0, 0};
+  DevJobInst ji{};
+  ji.addr = (uint64_t)(uintptr_t)f;
+  ji.n = h.n;
+  ji.stride = h.stride;
+  ji.degree = h.D;
+  ji.nt = 64 * waves;
+  LBM_HIP(hipMemcpyAsync(dcoef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
+  LBM_HIP(hipMemcpyAsync(dji, &ji, sizeof(ji), hipMemcpyHostToDevice, st));
+  LBM_HIP(launch_zero_ints(ints, 5, st));
+  LBM_HIP(launch_init(h.q, h.Dinit, h.prec, phi0, f, h.n, h.stride, dcoef, st));
+  for (int64_t left = steps; left > 0;) {
+    const int64_t now = std::min(left, kMaxStepsPerLaunch);
+    left -= now;
+    jb.steps = (int)now;
+    LBM_HIP(hipMemcpyAsync(djob, &jb, sizeof(jb), hipMemcpyHostToDevice, st));
+    LBM_HIP(hipStreamSynchronize(st));   // jb is reused by the next launch
+    LBM_HIP(launch_zero_ints(ints, 3, st));
+    LBM_HIP(launch_resident(h.q, h.prec, h.D, djob, dji, 1, 1, ints, ints + 1, ints + 2, dcoef, ints + 3, 0, -1, 1,
+                            ji.nt, lds, st));
+  }
+  LBM_HIP(launch_phi(h.prec, f, phi, h.n, h.stride, h.q, h.f32 ? h.mdl.phi_rest : 0.0, ints + 4, st));
+  int flags[2] = {0, 0};
+  LBM_HIP(hipMemcpyAsync(flags, ints + 3, sizeof(flags), hipMemcpyDeviceToHost, st));
+  LBM_HIP(hipStreamSynchronize(st));
+  if (flags[0] & 6) return LBM_ERR_TIMEOUT;
+  return (flags[0] || flags[1]) ? LBM_ERR_NONFINITE : LBM_OK;
 }
 
 }  // extern "C"

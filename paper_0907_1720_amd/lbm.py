@@ -124,6 +124,7 @@ def library() -> ctypes.CDLL:
         "lbm_create": (I32, [DP, P, P, SZ, P]),
         "lbm_load_phi": (I32, [P, P, I32]),
         "lbm_advance": (I32, [P, I64]),
+        "lbm_advance_noalloc": (I32, [DP, P, I64, P, P]),
         "lbm_advance_bounded": (I32, [P, I64, P, I32]),
         "lbm_advance_bounded_wave": (I32, [P, I64, P, I32]),
         "lbm_wave_rows": (I32, [P, I64, P, I32, P]),
@@ -242,6 +243,22 @@ def stability(p: Problem, phi_min: float, phi_max: float, steps: int):
     _check(library().lbm_stability(ctypes.byref(make_desc(p)), float(phi_min), float(phi_max), int(steps),
                                    ctypes.byref(g), ctypes.byref(a)), "lbm_stability")
     return g.value, a.value
+
+
+def advance_noalloc(p: Problem, phi0, steps: int, phi, stream: Optional[int] = None, allow_nonfinite: bool = False):
+    """lbm_advance_noalloc: phi := phi after `steps` steps from phi0 (device
+    tensors of p.n doubles, e.g. torch CUDA tensors), allocating nothing."""
+    for t in (phi0, phi):
+        if not (hasattr(t, "data_ptr") and getattr(t, "is_cuda", False)):
+            raise ValueError("phi0 and phi must be device tensors")
+        if t.numel() != p.n or t.element_size() != 8:
+            raise ValueError(f"expected {p.n} doubles")
+    d = make_desc(p)
+    st = _current_stream() if stream is None else int(stream)
+    s = library().lbm_advance_noalloc(ctypes.byref(d), int(phi0.data_ptr()), int(steps), int(phi.data_ptr()), st)
+    if not (allow_nonfinite and s == NONFINITE):
+        _check(s, "lbm_advance_noalloc")
+    return s
 
 
 def _current_stream() -> int:
