@@ -387,6 +387,22 @@ lbm_status lbm_server_submit(lbm_server s, const lbm_desc* d, const double* phi0
    Synchronises the stream.  Counts are optional outputs. */
 lbm_status lbm_server_step(lbm_server s, int32_t* active, int32_t* queued, int32_t* retired);
 
+/* Continuous batching without blocking the caller: if the round launched by
+   the previous call is still running on the device, return at once with
+   *running = 1; otherwise retire the requests it completed, admit queued
+   requests (as lbm_server_step) and launch the next round asynchronously
+   (*running = 1 if one was launched).  Call it often (a serving loop calls it
+   between arrivals); requests submitted while a round runs are admitted as
+   soon as it ends.  lbm_server_step and lbm_server_pump may be mixed: a step
+   first finishes a round a pump left running.  Counts are optional outputs
+   (active: admitted and not retired; queued: waiting for admission). */
+lbm_status lbm_server_pump(lbm_server s, int32_t* running, int32_t* active, int32_t* queued, int32_t* retired);
+
+/* Host timing of a retired request (steady clock): *queue_s from submission to
+   admission, *service_s from admission to retirement.  LBM_ERR_BUSY while it
+   is queued or running; optional outputs. */
+lbm_status lbm_server_timing(lbm_server s, int64_t id, double* queue_s, double* service_s);
+
 /* Result of request id: LBM_OK with phi in out[0..n) (n >= the request's node
    count) and its own status (LBM_OK / LBM_ERR_NONFINITE / LBM_ERR_TIMEOUT)
    once retired; LBM_ERR_BUSY while queued or running.  A request whose

@@ -4,6 +4,9 @@
 //
 //  k_phi       phi = sum_j f_j  (FP64)
 //  k_sum       FP64 sum of phi over a grid, deterministic two-pass
+#include <mutex>
+#include <unordered_map>
+
 #include "kernels.hpp"
 #include "kernels_table.hpp"
 
@@ -106,17 +109,34 @@ hipError_t launch_resident(int q, int prec, int code, const DevJob* jobs, const 
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, s);
 }
 
+namespace {
+// kernel attributes, queried once per kernel (the planner asks per instance)
+bool kernel_attributes(const void* fn, hipFuncAttributes* out) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, hipFuncAttributes> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(fn);
+  if (it == cache.end()) {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, fn) != hipSuccess) return false;
+    it = cache.emplace(fn, a).first;
+  }
+  *out = it->second;
+  return true;
+}
+}  // namespace
+
 int resident_vgprs(int q, int prec, int code) {
   hipFuncAttributes a;
   const void* fn = resident_kernel(q, prec, code);
-  if (!fn || hipFuncGetAttributes(&a, fn) != hipSuccess || a.numRegs <= 0) return 128;
+  if (!fn || !kernel_attributes(fn, &a) || a.numRegs <= 0) return 128;
   return a.numRegs;
 }
 
 size_t resident_static_lds(int q, int prec, int code) {
   hipFuncAttributes a;
   const void* fn = resident_kernel(q, prec, code);
-  if (!fn || hipFuncGetAttributes(&a, fn) != hipSuccess) return 1024;
+  if (!fn || !kernel_attributes(fn, &a)) return 1024;
   return a.sharedSizeBytes;
 }
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -128,7 +129,8 @@ struct lbm_batch_s {
   DevTile* tiles = nullptr;
   DevTile* tiles_host = nullptr;
   int tiles_cap = 0;
-  DevTileInst* tinsts = nullptr;
+  DevTileInst* tinsts = nullptr;       // two slots of tinsts_cap records
+  int tinsts_cap = 0;
   DevSlab* slabs = nullptr;           // two slots of slabs_cap records
   DevSlab* slabs_host = nullptr;
   int slabs_cap = 0;
@@ -375,6 +377,7 @@ lbm_status alloc_tables(lbm_batch_s* b, size_t maxn) {
     LBM_HIP(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
   }
   LBM_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+  b->tinsts_cap = count;
   if (hipMalloc(&b->tinsts, sizeof(DevTileInst) * 2 * count) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
   if (hipHostMalloc((void**)&b->tinsts_host, sizeof(DevTileInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
     return LBM_ERR_OUT_OF_MEMORY;
@@ -479,6 +482,8 @@ bool fits_resident(const lbm_batch_s* b, const HostInst& h) {
   return (size_t)lds_stride(h.q) * h.n * elem_size(h) + resident_static_lds(h.q, h.prec, h.D) <= b->lim.lds_max;
 }
 
+
+
 // The step-block graph of instance i for its current buffer, built on first use
 // and rebuilt when the instance's buffers, coefficients or shape changed.
 lbm_status step_graph(lbm_batch_s* b, int i, StepGraph** out) {
@@ -553,6 +558,7 @@ long long wait_ticks(const lbm_batch_s* b, int64_t steps) {
 constexpr int kChunkItems = 16;        // queue items per workgroup when jobs outnumber workgroups
 constexpr int64_t kMinChunkSteps = 256;
 constexpr int kMaxChunks = 64;
+constexpr int64_t kMinSlabChunk = 256;   // steps of one chunk of a slab launch
 
 // One pass: every instance advances by steps[i] <= kMaxStepsPerLaunch.
 lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
@@ -618,16 +624,16 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const size_t es = pr ? sizeof(float) : sizeof(double);
       const int q = std::get<0>(group.first);
       auto bytes_of = [&](int i) { return ((size_t)lds_stride(q) * b->inst[i].n * es + 15) / 16 * 16; };
-      // jobs: first-fit decreasing bin packing of equal-step instances into a
-      // workgroup's LDS share (half the LDS, or the largest instance)
-      // jobs hold instances of one variant and one step count
+      // a workgroup's LDS share: half the LDS, or the largest instance
+      size_t cap = b->lim.lds_max / 2;
+      for (int i : g) cap = std::max(cap, bytes_of(i));
+      // jobs: first-fit decreasing bin packing of equal-step instances into the
+      // LDS share; jobs hold instances of one variant and one step count
       std::stable_sort(g.begin(), g.end(), [&](int a, int c) {
         if (steps[a] != steps[c]) return steps[a] > steps[c];
         if (b->inst[a].D != b->inst[c].D) return b->inst[a].D < b->inst[c].D;
         return bytes_of(a) > bytes_of(c);
       });
-      size_t cap = b->lim.lds_max / 2;
-      for (int i : g) cap = std::max(cap, bytes_of(i));
       // waves per job: the waves a CU can hold at this kernel's register use,
       // shared by the jobs whose LDS fits on one CU
       const int vgprs = std::max(1, resident_vgprs(q, pr, code));
@@ -636,25 +642,35 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int kJobWaves = std::max(1, std::min(16, cu_waves / jobs_per_cu));
       // a pass that leaves most CUs idle (latency regime) gives every instance a
       // job of its own and up to a wave per 64 nodes: its steps end sooner
-      const int kJobInstances = latency ? 1 : std::min(kMaxJobInstances, kJobWaves);
       const int kNodesPerWave = latency ? 64 : 128;
       struct Bin { int64_t steps; int variant; size_t bytes; std::vector<int> members; };
       std::vector<Bin> bins;
-      size_t open_from = 0;   // bins before this index have another step count or variant
-      for (int i : g) {
-        if (!bins.empty() && (bins.back().steps != steps[i] || bins.back().variant != b->inst[i].D))
-          open_from = bins.size();
-        bool placed = false;
-        for (size_t u = open_from; u < bins.size() && !placed; ++u) {
-          Bin& bn = bins[u];
-          if (bn.bytes + bytes_of(i) <= cap && (int)bn.members.size() < kJobInstances) {
-            bn.bytes += bytes_of(i);
-            bn.members.push_back(i);
-            placed = true;
+      auto pack = [&](int max_inst) {
+        bins.clear();
+        size_t open_from = 0;   // bins before this index have another step count or variant
+        for (int i : g) {
+          if (!bins.empty() && (bins.back().steps != steps[i] || bins.back().variant != b->inst[i].D))
+            open_from = bins.size();
+          bool placed = false;
+          for (size_t u = open_from; u < bins.size() && !placed; ++u) {
+            Bin& bn = bins[u];
+            if (bn.bytes + bytes_of(i) <= cap && (int)bn.members.size() < max_inst) {
+              bn.bytes += bytes_of(i);
+              bn.members.push_back(i);
+              placed = true;
+            }
           }
+          if (!placed) bins.push_back(Bin{steps[i], b->inst[i].D, bytes_of(i), {i}});
         }
-        if (!placed) bins.push_back(Bin{steps[i], b->inst[i].D, bytes_of(i), {i}});
-      }
+      };
+      pack(latency ? 1 : std::min(kMaxJobInstances, kJobWaves));
+      // fewer jobs than the GPU holds at once (jobs_per_cu per CU) leave CUs
+      // idle for the whole pass: cap the instances per job so that there are
+      // enough (1024 instances of 1024 FP32 D1Q5 nodes would otherwise make
+      // 256 half-LDS jobs for 512 slots)
+      const int slots = jobs_per_cu * b->lim.cus;
+      if (!latency && (int)bins.size() < slots && (int)g.size() > (int)bins.size())
+        pack(std::max(1, ((int)g.size() + slots - 1) / slots));
       Launch L{q, pr, code, njobs, 0, 0, 64, 0};
       struct Planned { const Bin* bin; std::vector<int> waves; double est; };
       std::vector<Planned> plan;
@@ -732,12 +748,20 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   struct TileGroup { int q; int prec; int first, ntiles, tfirst, tcount, s, halo, launches, block; size_t lds; };
   std::vector<TileGroup> tgroups;
   std::vector<DevTile> tvec;
-  DevTileInst* htin = b->tinsts_host + (size_t)k * count;
+  // tile-instance records of this pass (the tiled path: one per instance; the
+  // slab path: one per instance and step chunk), copied to slot k below
+  std::vector<DevTileInst> htin;
   int tin_used = 0;
   // slab plan per (q, prec): cooperative launches of at most `capacity` slabs
   // (every workgroup of a launch resident at once), run one after another on
   // one lane; an instance whose slabs exceed one launch, or whose slabs would
-  // be narrower than a halo, goes to temporal blocking instead
+  // be narrower than a halo, goes to temporal blocking instead.  When a
+  // group's instances need several launches, their steps are split into
+  // chunks and the (instance, chunk) items fill the launches in chunk-major
+  // order: every launch but the last is full, and the last one is short only
+  // by part of a chunk (without chunks, a last launch with a few instances
+  // costs a whole launch's time).  An instance's chunk c + 1 always lies in a
+  // later launch than its chunk c, which the lane's order serialises.
   struct SlabLaunch { int q; int prec; int code; int first, count, cap, s, halo, block; size_t lds; size_t xoff; int foff; };
   std::vector<SlabLaunch> slaunch;
   std::vector<DevSlab> svec;
@@ -765,6 +789,9 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int capacity = std::min(per_cu * b->lim.cus, kMaxSlabs);
       if (per_cu > 0) min_per_cu = std::min(min_per_cu, per_cu);
       SlabLaunch L{q, pr, code, (int)svec.size(), 0, capacity, sp, halo, block, lds, 0, 0};
+      // the instances that take slabs, their slab counts and core widths
+      std::vector<std::pair<int, int>> mem;   // (instance, slabs)
+      int64_t total = 0, maxsteps = 0;
       for (int i : g) {
         const HostInst& h = b->inst[i];
         const int ks = cmax > 0 ? (h.n + cmax - 1) / cmax : 0;
@@ -773,32 +800,55 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
           til[qq][pr].push_back(i);
           continue;
         }
-        if (L.count + ks > capacity) {
-          slaunch.push_back(L);
-          L.first = (int)svec.size();
-          L.count = 0;
+        mem.push_back({i, ks});
+        total += ks;
+        maxsteps = std::max<int64_t>(maxsteps, steps[i]);
+      }
+      // step chunks: the fewest (at most 8, each >= kMinSlabChunk steps) whose
+      // launches waste at most 1/20 of a launch per launch
+      int nch = 1;
+      if (total > capacity && maxsteps >= 2 * kMinSlabChunk) {
+        for (int c = 1; c <= 8 && maxsteps / c >= kMinSlabChunk; ++c) {
+          const double launches = std::ceil((double)(c * total) / capacity);
+          nch = c;
+          if (launches - (double)(c * total) / capacity <= 0.05 * launches) break;
         }
-        DevTileInst& ti = htin[tin_used];
-        ti.off = h.off;
-        ti.n = h.n;
-        ti.stride = h.stride;
-        ti.steps = (int)steps[i];
-        ti.cur0 = h.cur;
-        ti.degree = h.D;
-        ti.inst = i;
-        for (int m = 0; m < ks; ++m) {
-          DevSlab sl;
-          sl.ti = tin_used;
-          sl.x0 = m * core;
-          sl.core = std::min(core, h.n - m * core);
-          sl.left = L.count + (m + ks - 1) % ks;
-          sl.right = L.count + (m + 1) % ks;
-          sl.pad_ = 0;
-          svec.push_back(sl);
+      }
+      for (int c = 0; c < nch; ++c) {
+        for (const auto& [i, ks] : mem) {
+          const HostInst& h = b->inst[i];
+          const int64_t base = steps[i] / nch, rem = steps[i] % nch;
+          const int64_t st = base + (c < rem ? 1 : 0);
+          if (st == 0) continue;
+          const int core = (h.n + ks - 1) / ks;
+          if (L.count + ks > capacity) {
+            slaunch.push_back(L);
+            L.first = (int)svec.size();
+            L.count = 0;
+          }
+          DevTileInst ti{};
+          ti.off = h.off;
+          ti.n = h.n;
+          ti.stride = h.stride;
+          ti.steps = (int)st;
+          ti.cur0 = h.cur ^ (c & 1);   // each earlier chunk flipped the buffer once
+          ti.degree = h.D;
+          ti.inst = i;
+          htin.push_back(ti);
+          for (int m = 0; m < ks; ++m) {
+            DevSlab sl;
+            sl.ti = tin_used;
+            sl.x0 = m * core;
+            sl.core = std::min(core, h.n - m * core);
+            sl.left = L.count + (m + ks - 1) % ks;
+            sl.right = L.count + (m + 1) % ks;
+            sl.pad_ = 0;
+            svec.push_back(sl);
+          }
+          L.count += ks;
+          ++tin_used;
+          if (c == 0) slab_insts.push_back(i);
         }
-        L.count += ks;
-        ++tin_used;
-        slab_insts.push_back(i);
       }
       if (L.count) slaunch.push_back(L);
     }
@@ -826,6 +876,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   if (latency && slaunch.size() > 1 && !slab_side_by_side && 2 * total_slabs < total_cap) {
     for (int i : slab_insts) til[b->inst[i].q][b->inst[i].prec].push_back(i);
     tin_used = tin_slab0;
+    htin.resize(tin_slab0);
     svec.clear();
     slaunch.clear();
     xbuf_need = 0;
@@ -892,7 +943,8 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       int maxcore = 1;
       for (int i : g) {
         const HostInst& h = b->inst[i];
-        DevTileInst& ti = htin[tin_used];
+        htin.emplace_back();
+        DevTileInst& ti = htin.back();
         ti.off = h.off;
         ti.n = h.n;
         ti.stride = h.stride;
@@ -954,8 +1006,24 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
                            hipMemcpyHostToDevice, b->stream));
   }
   if (tin_used) {
-    DevTileInst* dti = b->tinsts + (size_t)k * count;
-    LBM_HIP(hipMemcpyAsync(dti, htin, sizeof(DevTileInst) * tin_used, hipMemcpyHostToDevice, b->stream));
+    if (tin_used > b->tinsts_cap) {
+      // grow both slots; earlier passes must be done with them
+      LBM_HIP(hipStreamSynchronize(b->stream));
+      hipFree(b->tinsts);
+      hipHostFree(b->tinsts_host);
+      b->tinsts = nullptr;
+      b->tinsts_host = nullptr;
+      b->tinsts_cap = 0;
+      const int cap = 2 * tin_used;
+      if (hipMalloc(&b->tinsts, sizeof(DevTileInst) * 2 * cap) != hipSuccess) return LBM_ERR_OUT_OF_MEMORY;
+      if (hipHostMalloc((void**)&b->tinsts_host, sizeof(DevTileInst) * 2 * cap, hipHostMallocDefault) != hipSuccess)
+        return LBM_ERR_OUT_OF_MEMORY;
+      b->tinsts_cap = cap;
+    }
+    DevTileInst* hti = b->tinsts_host + (size_t)k * b->tinsts_cap;
+    std::memcpy(hti, htin.data(), sizeof(DevTileInst) * tin_used);
+    DevTileInst* dti = b->tinsts + (size_t)k * b->tinsts_cap;
+    LBM_HIP(hipMemcpyAsync(dti, hti, sizeof(DevTileInst) * tin_used, hipMemcpyHostToDevice, b->stream));
   }
   DevJobInst* ditems = b->items + (size_t)k * b->items_cap;
   DevJob* djobs = b->jobs + (size_t)k * b->items_cap;
@@ -1005,7 +1073,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
     ++lane;
     DevTile* dt = b->tiles + (size_t)k * b->tiles_cap + G.first;
-    DevTileInst* dti = b->tinsts + (size_t)k * count;
+    DevTileInst* dti = b->tinsts + (size_t)k * b->tinsts_cap;
     void* b0 = G.prec ? (void*)b->f32[0] : (void*)b->f64[0];
     void* b1 = G.prec ? (void*)b->f32[1] : (void*)b->f64[1];
     for (int l = 0; l < G.launches; ++l)
@@ -1024,7 +1092,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   // unless all of them fit the GPU twice over
   if (!slaunch.empty()) {
     const DevSlab* ds = b->slabs + (size_t)k * b->slabs_cap;
-    const DevTileInst* dti = b->tinsts + (size_t)k * count;
+    const DevTileInst* dti = b->tinsts + (size_t)k * b->tinsts_cap;
     hipStream_t st = nullptr;
     for (size_t l = 0; l < slaunch.size(); ++l) {
       if (l == 0 || slab_side_by_side) {
@@ -1861,6 +1929,10 @@ struct Arena {
   }
 };
 
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 struct Request {
   int64_t id;
   lbm_desc desc;
@@ -1878,6 +1950,7 @@ struct Slot {
 struct Result {
   std::vector<double> phi;
   lbm_status status;
+  double t_submit = 0.0, t_admit = 0.0, t_retire = 0.0;   // host steady clock
 };
 
 size_t state_bytes_of(const lbm_desc& d) {
@@ -1901,6 +1974,10 @@ struct lbm_server_s {
   std::vector<int64_t> steps_buf;
   double node_updates = 0.0;
   double device_ms = 0.0;
+  // a round launched and not yet retired (lbm_server_pump): its node updates
+  bool inflight = false;
+  bool inflight_empty = false;   // the round advanced nothing (only zero-step requests)
+  double inflight_nu = 0.0;
 };
 
 extern "C" {
@@ -1966,19 +2043,20 @@ lbm_status lbm_server_submit(lbm_server sv, const lbm_desc* d, const double* phi
   r.steps = steps;
   sv->queue.push_back(std::move(r));
   sv->results.emplace_back();
+  sv->results.back().t_submit = now_s();
   sv->done.push_back(0);
   *id = sv->queue.back().id;
   return LBM_OK;
 }
 
-// One scheduling round: admit queued requests (FIFO) while a slot and arena
-// space are free, advance every active request by min(block, remaining) steps
-// in one planner pass (persistent resident launches per LDS class, tiled groups,
-// all concurrent), then retire finished requests and free their space.
-lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int32_t* retired) {
-  if (!sv) return LBM_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// Admission: queued requests in arrival order while a slot and arena space
+// are free (f := f_eq(phi0) on the stream, which it synchronises).
+void server_admit(lbm_server_s* sv) {
   lbm_batch_s* b = sv->b;
-  // admission
   size_t qi = 0;
   for (; qi < sv->queue.size(); ++qi) {
     Request& r = sv->queue[qi];
@@ -1998,12 +2076,15 @@ lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int3
       h.off = (int64_t)(off / (h.f32 ? sizeof(float) : sizeof(double)));
       s = load_phi_one(b, slot, r.phi0.data(), 0);
     }
+    Result& res = sv->results[r.id - 1];
+    res.t_admit = now_s();
     if (s != LBM_OK) {
       // submission ran the same checks, so this is a device error: the request
       // retires with it (no phi) and the queue moves on
       sv->arena.release(off, bytes);
       h = HostInst();
-      sv->results[r.id - 1].status = s;
+      res.status = s;
+      res.t_retire = res.t_admit;
       sv->done[r.id - 1] = 1;
       continue;
     }
@@ -2015,11 +2096,16 @@ lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int3
     sl.bytes = bytes;
   }
   sv->queue.erase(sv->queue.begin(), sv->queue.begin() + qi);
-  // one block.  A round lasts as long as its slowest request's block; requests
-  // whose steps take less time take proportionally more steps in the same
-  // round, up to 8 blocks.  A step's time is estimated as its arithmetic per
-  // node (lattice size x polynomial degree) times the node sweeps of one
-  // workgroup (1024 threads; larger grids are spread over several)
+}
+
+// One block for every active request in one planner pass (asynchronous on
+// the stream).  A round lasts as long as its slowest request's block;
+// requests whose steps take less time take proportionally more steps in the
+// same round, up to 8 blocks.  A step's time is estimated as its arithmetic
+// per node (lattice size x polynomial degree) times the node sweeps of one
+// workgroup (1024 threads; larger grids are spread over several).
+lbm_status server_launch(lbm_server_s* sv, int* act_out) {
+  lbm_batch_s* b = sv->b;
   auto step_cost = [&](size_t k) {
     const HostInst& h = b->inst[k];
     const int sweeps = (std::min(h.n, 4096) + 1023) / 1024;
@@ -2039,20 +2125,36 @@ lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int3
       nu += (double)sv->steps_buf[k] * b->inst[k].n;
     }
   }
-  if (act) {
+  *act_out = act;
+  if (!act) return LBM_OK;
+  sv->inflight_empty = nu == 0.0;
+  if (!sv->inflight_empty) {
     lbm_status s = advance(b, sv->steps_buf.data());
     if (s != LBM_OK) return s;
+  }
+  sv->inflight = true;
+  sv->inflight_nu = nu;
+  return LBM_OK;
+}
+
+// The launched round has finished on the device: account for it, retire the
+// requests it completed (phi read out, space released).
+lbm_status server_finish(lbm_server_s* sv, int* retired) {
+  lbm_batch_s* b = sv->b;
+  if (!sv->inflight_empty) {
     float ms = 0.0f;
     LBM_HIP(hipEventSynchronize(b->ev1));
     if (hipEventElapsedTime(&ms, b->ev0, b->ev1) == hipSuccess) sv->device_ms += ms;
-    sv->node_updates += nu;
   }
-  // retirement
+  sv->node_updates += sv->inflight_nu;
+  sv->inflight = false;
+  sv->inflight_nu = 0.0;
   int ret = 0;
   for (size_t k = 0; k < sv->slots.size(); ++k) {
     Slot& sl = sv->slots[k];
     if (!sl.active) continue;
     sl.remaining -= sv->steps_buf[k];
+    sv->steps_buf[k] = 0;
     if (sl.remaining > 0) continue;
     Result& res = sv->results[sl.id - 1];
     res.phi.resize(b->inst[k].n);
@@ -2060,14 +2162,86 @@ lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int3
     lbm_status s = read_phi(b, (int)k, res.phi.data(), 0, &st);
     if (s != LBM_OK && s != LBM_ERR_NONFINITE && s != LBM_ERR_TIMEOUT) return s;
     res.status = st;
+    res.t_retire = now_s();
     sv->done[sl.id - 1] = 1;
     sv->arena.release(sl.off, sl.bytes);
     sl = Slot();
     ++ret;
   }
-  if (active) *active = act - ret;
+  *retired = ret;
+  return LBM_OK;
+}
+
+void server_counts(const lbm_server_s* sv, int32_t* active, int32_t* queued) {
+  int act = 0;
+  for (const Slot& sl : sv->slots) act += sl.active ? 1 : 0;
+  if (active) *active = act;
   if (queued) *queued = (int32_t)sv->queue.size();
+}
+
+}  // namespace
+
+extern "C" {
+
+// One synchronous scheduling round: finish a round a pump left running,
+// admit, advance every active request by one block (all concurrent on the
+// device), wait, retire.
+lbm_status lbm_server_step(lbm_server sv, int32_t* active, int32_t* queued, int32_t* retired) {
+  if (!sv) return LBM_ERR_INVALID_ARG;
+  int ret = 0, r = 0, act = 0;
+  if (sv->inflight) {
+    lbm_status s = server_finish(sv, &r);
+    if (s != LBM_OK) return s;
+    ret += r;
+  }
+  server_admit(sv);
+  lbm_status s = server_launch(sv, &act);
+  if (s != LBM_OK) return s;
+  if (sv->inflight) {
+    s = server_finish(sv, &r);
+    if (s != LBM_OK) return s;
+    ret += r;
+  }
+  server_counts(sv, active, queued);
   if (retired) *retired = ret;
+  return LBM_OK;
+}
+
+// Continuous batching without blocking the caller: while a round runs on the
+// device, return at once (*running = 1); once it has finished, retire what it
+// completed, admit queued requests and launch the next round.
+lbm_status lbm_server_pump(lbm_server sv, int32_t* running, int32_t* active, int32_t* queued, int32_t* retired) {
+  if (!sv) return LBM_ERR_INVALID_ARG;
+  int ret = 0, act = 0;
+  if (sv->inflight && !sv->inflight_empty) {
+    const hipError_t q = hipEventQuery(sv->b->ev1);
+    if (q == hipErrorNotReady) {
+      if (running) *running = 1;
+      server_counts(sv, active, queued);
+      if (retired) *retired = 0;
+      return LBM_OK;
+    }
+    if (q != hipSuccess) return LBM_ERR_DEVICE;
+  }
+  if (sv->inflight) {
+    lbm_status s = server_finish(sv, &ret);
+    if (s != LBM_OK) return s;
+  }
+  server_admit(sv);
+  lbm_status s = server_launch(sv, &act);
+  if (s != LBM_OK) return s;
+  if (running) *running = sv->inflight ? 1 : 0;
+  server_counts(sv, active, queued);
+  if (retired) *retired = ret;
+  return LBM_OK;
+}
+
+lbm_status lbm_server_timing(lbm_server sv, int64_t id, double* queue_s, double* service_s) {
+  if (!sv || id < 1 || id >= sv->next_id) return LBM_ERR_INVALID_ARG;
+  if (sv->done[id - 1] == 0) return LBM_ERR_BUSY;
+  const Result& r = sv->results[id - 1];
+  if (queue_s) *queue_s = r.t_admit - r.t_submit;
+  if (service_s) *service_s = r.t_retire - r.t_admit;
   return LBM_OK;
 }
 

@@ -154,6 +154,8 @@ def library() -> ctypes.CDLL:
         "lbm_server_submit": (I32, [P, DP, P, I64, P]),
         "lbm_server_step": (I32, [P, P, P, P]),
         "lbm_server_poll": (I32, [P, I64, P, I64, P]),
+        "lbm_server_pump": (I32, [P, P, P, P, P]),
+        "lbm_server_timing": (I32, [P, I64, P, P]),
         "lbm_server_stats": (I32, [P, P, P, P]),
         "lbm_server_destroy": (I32, [P]),
     }
@@ -530,6 +532,22 @@ class Server:
         _check(library().lbm_server_step(self._h, ctypes.byref(a), ctypes.byref(q), ctypes.byref(r)),
                "lbm_server_step")
         return a.value, q.value, r.value
+
+    def pump(self):
+        """Non-blocking round management; returns (running, active, queued, retired)."""
+        r, a, q, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(library().lbm_server_pump(self._h, ctypes.byref(r), ctypes.byref(a), ctypes.byref(q),
+                                         ctypes.byref(t)), "lbm_server_pump")
+        return r.value, a.value, q.value, t.value
+
+    def timing(self, rid: int):
+        """(queue seconds, service seconds) of a retired request, else None."""
+        qs, ss = ctypes.c_double(), ctypes.c_double()
+        s = library().lbm_server_timing(self._h, int(rid), ctypes.byref(qs), ctypes.byref(ss))
+        if s == BUSY:
+            return None
+        _check(s, "lbm_server_timing")
+        return qs.value, ss.value
 
     def poll(self, rid: int):
         """(phi, status) once request rid has finished, else None."""

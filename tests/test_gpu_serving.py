@@ -180,3 +180,64 @@ def test_extension_models_served_alongside_the_mix():
             err = rel2(phi, want)
             say("    vs oracle", f"{err:.2e}")
             assert err <= tol, (k, p.name, err)
+
+
+def test_pump_admits_requests_submitted_while_a_round_runs():
+    """lbm_server_pump: rounds run without blocking the caller; requests
+    submitted while one runs are admitted when it ends; every result equals
+    its solo solve bit for bit and carries its queue and service times."""
+    import time
+    reqs = _requests(16, n_max=1500, steps_max=1200, start=700)
+    srv = lbm.Server(128 << 20, max_slots=6, max_n=2048, block_steps=150)
+    ids = [srv.submit(r.problem, r.phi0, r.steps) for r in reqs[:4]]
+    running, active, queued, _ = srv.pump()
+    assert running == 1 and active == 4 and queued == 0
+    saw_running = False
+    got = {}
+    k = 4
+    t_end = time.perf_counter() + 120
+    while len(got) < len(reqs):
+        assert time.perf_counter() < t_end
+        if k < len(reqs):   # one new request per pump call while work remains
+            ids.append(srv.submit(reqs[k].problem, reqs[k].phi0, reqs[k].steps))
+            k += 1
+        running, active, queued, retired = srv.pump()
+        saw_running |= running == 1 and k < len(reqs)
+        for j, rid in enumerate(ids):
+            if j not in got:
+                res = srv.poll(rid)
+                if res is not None:
+                    got[j] = res
+        time.sleep(1e-4)
+    assert saw_running
+    nu, _, free = srv.stats()
+    assert nu == sum(r.problem.n * r.steps for r in reqs)
+    for j, r in enumerate(reqs):
+        phi, st = got[j]
+        assert st == lbm.OK
+        assert np.array_equal(phi, _alone(r)), (j, r.problem.name)
+        qs, ss = srv.timing(ids[j])
+        assert qs >= 0.0 and ss > 0.0
+    # a step after pumps finishes cleanly with nothing left
+    assert srv.step() == (0, 0, 0)
+    srv.close()
+
+
+def test_mixed_step_and_pump_and_zero_step_requests():
+    reqs = _requests(6, n_max=900, steps_max=600, start=760)
+    srv = lbm.Server(64 << 20, max_slots=8, max_n=1024, block_steps=100)
+    ids = [srv.submit(r.problem, r.phi0, r.steps) for r in reqs]
+    zero = srv.submit(reqs[0].problem, reqs[0].phi0, 0)
+    srv.pump()      # launches a round
+    srv.step()      # finishes it, runs a full round synchronously
+    for _ in range(100000):
+        running, active, queued, _ = srv.pump()
+        if not running and active == 0 and queued == 0:
+            break
+    res = [srv.poll(i) for i in ids]
+    assert all(r is not None and r[1] == lbm.OK for r in res)
+    for r, q in zip(res, reqs):
+        assert np.array_equal(r[0], _alone(q))
+    z = srv.poll(zero)
+    assert z is not None and np.array_equal(z[0], _alone(dataclasses.replace(reqs[0], steps=0)))
+    srv.close()
