@@ -782,10 +782,20 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       while (sp > 2 && W - 2 * sp * H < 2 * sp * H) sp -= 2;
       const int halo = sp * H;
       const int cmax = W - 2 * halo;
-      const int block = std::min(1024, std::max(64, (W / 2 + 63) / 64 * 64));
+      // two or more nodes per thread; if the kernel's registers do not let
+      // `wgs` workgroups of that size share a CU (its LDS is cut for wgs), halve
+      // the workgroup until they do, so no part of the LDS stays unused
+      int block = std::min(1024, std::max(64, (W / 2 + 63) / 64 * 64));
       const size_t lds = (size_t)W * lds_stride(q) * es + 16;
       int per_cu = 0;
       if (cmax < halo || slab_occupancy(q, pr, code, block, lds, &per_cu) != hipSuccess) per_cu = 0;
+      while (per_cu > 0 && per_cu < wgs && block > 256) {
+        int pc = 0;
+        const int nb = (block / 2 + 63) / 64 * 64;
+        if (slab_occupancy(q, pr, code, nb, lds, &pc) != hipSuccess || pc <= per_cu) break;
+        block = nb;
+        per_cu = pc;
+      }
       const int capacity = std::min(per_cu * b->lim.cus, kMaxSlabs);
       if (per_cu > 0) min_per_cu = std::min(min_per_cu, per_cu);
       SlabLaunch L{q, pr, code, (int)svec.size(), 0, capacity, sp, halo, block, lds, 0, 0};
@@ -804,15 +814,35 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
         total += ks;
         maxsteps = std::max<int64_t>(maxsteps, steps[i]);
       }
-      // step chunks: the fewest (at most 8, each >= kMinSlabChunk steps) whose
-      // launches waste at most 1/20 of a launch per launch
+      // step chunks: a launch lasts about its chunk's steps whatever its fill,
+      // so c chunks cost (launches needed for c chunks) / c; take the fewest
+      // chunks (at most 8, each >= kMinSlabChunk steps) within 3% of the
+      // cheapest, counting launches by packing whole instances as below
       int nch = 1;
       if (total > capacity && maxsteps >= 2 * kMinSlabChunk) {
+        auto launches_for = [&](int c) {
+          int nl = 1, fill = 0;
+          for (int r = 0; r < c; ++r)
+            for (const auto& m : mem) {
+              if (fill + m.second > capacity) {
+                ++nl;
+                fill = 0;
+              }
+              fill += m.second;
+            }
+          return nl;
+        };
+        double best = 1e30;
+        std::vector<double> cost(9, 1e30);
         for (int c = 1; c <= 8 && maxsteps / c >= kMinSlabChunk; ++c) {
-          const double launches = std::ceil((double)(c * total) / capacity);
-          nch = c;
-          if (launches - (double)(c * total) / capacity <= 0.05 * launches) break;
+          cost[c] = (double)launches_for(c) / c;
+          best = std::min(best, cost[c]);
         }
+        for (int c = 1; c <= 8; ++c)
+          if (cost[c] <= 1.03 * best) {
+            nch = c;
+            break;
+          }
       }
       for (int c = 0; c < nch; ++c) {
         for (const auto& [i, ks] : mem) {
