@@ -177,9 +177,15 @@ template <int Q, int D, int P, typename T, typename A>
 struct Relaxer {
   static constexpr int K = P == 0 ? D + 1 : (D + 1) / 2;   // coefficients per population
   static constexpr bool kRest = (sizeof(T) == 4 && sizeof(A) == 8);
+  // the lower coefficients are held in scalar registers when they fit, so that
+  // every code path of a kernel (the node loop, a masked or wrapped node) reads
+  // the same registers instead of reloading the table
+  static constexpr bool kPin = P < 2 && Q * (K - 1) * (int)sizeof(A) / 4 <= 52;
   const A* __restrict__ c;   // [Q][kRow]: dense, or the odd degrees compacted
   const DevCoef* __restrict__ cfp;   // power-sum tables (P = 2)
   A top[Q];
+  A low[kPin ? Q : 1][kPin ? K - 1 : 1];
+  A add[kPin && kRest && P == 1 ? Q : 1];   // -omega f_rest_j of the odd tables (FP32 storage)
   A w0;
   double s0;                 // phi_rest (odd tables with FP32 storage)
   const double* __restrict__ cst;
@@ -197,6 +203,40 @@ struct Relaxer {
         asm volatile("" : "+v"(top[j]));
       }
     }
+    if constexpr (kPin) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j)
+#pragma unroll
+        for (int d = 0; d < K - 1; ++d) {
+          low[j][d] = c[j * kRow + d];
+#if defined(__HIP_DEVICE_COMPILE__)
+          asm volatile("" : "+s"(low[j][d]));   // device pass only: a register class of the GPU
+#endif
+        }
+      if constexpr (kRest && P == 1) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          add[j] = (A)cst[j];
+#if defined(__HIP_DEVICE_COMPILE__)
+          asm volatile("" : "+s"(add[j]));   // device pass only: a register class of the GPU
+#endif
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ A odd_add(int j) const {
+    if constexpr (!kRest)
+      return (A)0;
+    else if constexpr (kPin)
+      return add[j];
+    else
+      return (A)cst[j];
+  }
+  __device__ __forceinline__ A coef(int j, int d) const {
+    if constexpr (kPin)
+      return low[j][d];
+    else
+      return c[j * kRow + d];
   }
 
   __device__ __forceinline__ void operator()(T (&f)[Q]) const {
@@ -269,7 +309,7 @@ struct Relaxer {
       for (int j = 0; j < Q; ++j) {
         A acc = top[j];
 #pragma unroll
-        for (int d = K - 2; d >= 0; --d) acc = fma_a(acc, p, c[j * kRow + d]);
+        for (int d = K - 2; d >= 0; --d) acc = fma_a(acc, p, coef(j, d));
         f[j] = (T)fma_a(w0, (A)f[j], acc);
       }
     } else {
@@ -278,8 +318,8 @@ struct Relaxer {
       for (int j = 0; j < Q; ++j) {
         A acc = top[j];
 #pragma unroll
-        for (int k = K - 2; k >= 0; --k) acc = fma_a(acc, u, c[j * kRow + k]);
-        acc = fma_a(acc, p, kRest ? (A)cst[j] : (A)0);
+        for (int k = K - 2; k >= 0; --k) acc = fma_a(acc, u, coef(j, k));
+        acc = fma_a(acc, p, odd_add(j));
         f[j] = (T)fma_a(w0, (A)f[j], acc);
       }
     }

@@ -231,6 +231,26 @@ __device__ __forceinline__ void aa_sweep(T* __restrict__ S, int lo, int hi, int 
   }
 }
 
+// Nodes x, x + B, ..., x + (iters - 1) B, and x + iters B where `extra` holds
+// (the node set of aa_sweep over [lo, hi) when x = lo + t, iters = (hi - lo) / B
+// and extra = t < (hi - lo) mod B); `iters` is wave-uniform.  The loop runs on a
+// scalar counter and advances a pointer, so that a node costs one vector add
+// besides its update; the last pass masks the lanes without an extra node.
+template <int Q, bool ODD, typename T, typename R>
+__device__ __forceinline__ void aa_sweep_uniform(T* __restrict__ S, int x, int iters, bool extra, int B, const R& r) {
+  const int passes = iters + (__builtin_amdgcn_ballot_w64(extra) != 0 ? 1 : 0);
+  T* Sx = S + x * lds_stride(Q);
+  const int step = B * lds_stride(Q);
+  for (int k = 0; k < passes; ++k, Sx += step) {
+    if (k < iters || extra) {
+      if constexpr (ODD)
+        aa_odd<Q>(Sx, 0, r);
+      else
+        aa_even<Q>(Sx, 0, r);
+    }
+  }
+}
+
 // Initialisation polynomial of degree <= D (the kernel variant's degree bounds
 // the dense initialisation table; zeros above the table's own degree leave the
 // result bitwise equal to a Horner from its leading coefficient)
@@ -294,6 +314,9 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
   // interior odd sweeps give threads r..nt-1 one node less, r = (n - 2H) mod nt
   const int r = act ? (n - 2 * H) % nt : 0;
   const int seam0 = (r > 0 && r + 2 * H <= nt) ? r : 0;
+  // nodes per thread of the even sweep [0, n) and the odd interior sweep [H, n - H)
+  const int ne = act ? n / nt : 0, re = act ? n - ne * nt : 0;
+  const int no = act ? (n - 2 * H) / nt : 0;
   if (act)
     for (int j = 0; j < Q; ++j)
       for (int x = t; x < n; x += nt) S[x * lds_stride(Q) + j] = g[(int64_t)j * ji.stride + x];
@@ -301,9 +324,9 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
   for (int s = 0; s < steps; ++s) {
     if (act) {
       if ((s & 1) == 0) {
-        aa_sweep<Q, false, 1>(S, 0, n, t, nt, relax);
+        aa_sweep_uniform<Q, false>(S, t, ne, t < re, nt, relax);
       } else {
-        aa_sweep<Q, true, 1>(S, H, n - H, t, nt, relax);   // interior: no wrap
+        aa_sweep_uniform<Q, true>(S, H + t, no, t < r, nt, relax);   // interior: no wrap
         // the 2H seam nodes go to threads with one interior node less
         const int u = t - seam0;
         if (u >= 0 && u < 2 * H) aa_odd_wrap<Q>(S, u < H ? u : n - 2 * H + u, n, relax);
