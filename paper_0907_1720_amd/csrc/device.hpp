@@ -173,7 +173,8 @@ __device__ __forceinline__ double int_pow(double x, int k) {
   return r;
 }
 
-template <int Q, int D, int P, typename T, typename A>
+// V: the kernel has vector registers to spare for kNV > 1 (see below)
+template <int Q, int D, int P, typename T, typename A, bool V = false>
 struct Relaxer {
   static constexpr int K = P == 0 ? D + 1 : (D + 1) / 2;   // coefficients per population
   static constexpr bool kRest = (sizeof(T) == 4 && sizeof(A) == 8);
@@ -181,9 +182,22 @@ struct Relaxer {
   // every code path of a kernel (the node loop, a masked or wrapped node) reads
   // the same registers instead of reloading the table
   static constexpr bool kPin = P < 2 && Q * (K - 1) * (int)sizeof(A) / 4 <= 52;
+  // Larger tables keep their highest kNV coefficients per population in vector
+  // registers, enough that the rest (read as scalar operands) leave the kernel
+  // scalar registers for its own state: otherwise the node loop's operands
+  // push that state out to vector-register lanes and every step reloads it.
+  // (at most three per population: tables that would need more keep one)
+  static constexpr int nv_for_table() {
+    if (!V || P >= 2 || kPin) return 1;
+    for (int nv = 2; nv <= 3 && nv < K; ++nv)
+      if (Q * (K - nv) * (int)sizeof(A) / 4 <= 70) return nv;
+    return 1;
+  }
+  static constexpr int kNV = nv_for_table();
   const A* __restrict__ c;   // [Q][kRow]: dense, or the odd degrees compacted
   const DevCoef* __restrict__ cfp;   // power-sum tables (P = 2)
   A top[Q];
+  A topv[kNV > 1 ? kNV - 1 : 1][Q];   // coefficients K - 2, ..., K - kNV
   A low[kPin ? Q : 1][kPin ? K - 1 : 1];
   A add[kPin && kRest && P == 1 ? Q : 1];   // -omega f_rest_j of the odd tables (FP32 storage)
   A w0;
@@ -201,6 +215,11 @@ struct Relaxer {
       for (int j = 0; j < Q; ++j) {
         top[j] = c[j * kRow + K - 1];
         asm volatile("" : "+v"(top[j]));
+#pragma unroll
+        for (int v = 0; v + 1 < kNV; ++v) {
+          topv[v][j] = c[j * kRow + K - 2 - v];
+          asm volatile("" : "+v"(topv[v][j]));
+        }
       }
     }
     if constexpr (kPin) {
@@ -235,6 +254,8 @@ struct Relaxer {
   __device__ __forceinline__ A coef(int j, int d) const {
     if constexpr (kPin)
       return low[j][d];
+    else if (d > K - 1 - kNV)
+      return topv[K - 2 - d][j];
     else
       return c[j * kRow + d];
   }
@@ -341,9 +362,9 @@ template <> struct Relax<float, float> {
   __device__ static float w0(const DevCoef* c) { return c->w0f; }
 };
 
-template <int Q, int D, int P, typename T, typename A>
-__device__ __forceinline__ Relaxer<Q, D, P, T, A> make_relaxer(const DevCoef* __restrict__ cf) {
-  Relaxer<Q, D, P, T, A> r;
+template <int Q, int D, int P, typename T, typename A, bool V = false>
+__device__ __forceinline__ Relaxer<Q, D, P, T, A, V> make_relaxer(const DevCoef* __restrict__ cf) {
+  Relaxer<Q, D, P, T, A, V> r;
   r.init(Relax<T, A>::coef(cf), Relax<T, A>::w0(cf), cf);
   return r;
 }

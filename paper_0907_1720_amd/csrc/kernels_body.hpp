@@ -251,6 +251,26 @@ __device__ __forceinline__ void aa_sweep_uniform(T* __restrict__ S, int x, int i
   }
 }
 
+// Sweep of [lo, hi) (lo + t, lo + t + B, ...) with the loop that suits the
+// variant: the uniform loop when the equilibrium's coefficients sit in scalar
+// registers or the power-sum body reads them once per node (there the masked
+// last pass costs nothing), else the per-lane loop -- a masked node body that
+// must reload a large table spends more than the loop control it saves.
+// `iters` and `extra` describe [lo, hi) as in aa_sweep_uniform.
+template <int Q, int D, int P, typename T, typename A>
+constexpr bool uniform_sweep() {
+  return Relaxer<Q, D, P, T, A>::kPin || P == 3;   // (kPin does not depend on V)
+}
+
+template <int Q, int D, int P, typename A, bool ODD, typename T, typename R>
+__device__ __forceinline__ void aa_sweep_range(T* __restrict__ S, int lo, int hi, int t, int B, int iters, bool extra,
+                                               const R& r) {
+  if constexpr (uniform_sweep<Q, D, P, T, A>())
+    aa_sweep_uniform<Q, ODD>(S, lo + t, iters, extra, B, r);
+  else
+    aa_sweep<Q, ODD, 1>(S, lo, hi, t, B, r);
+}
+
 // Initialisation polynomial of degree <= D (the kernel variant's degree bounds
 // the dense initialisation table; zeros above the table's own degree leave the
 // result bitwise equal to a Horner from its leading coefficient)
@@ -310,7 +330,8 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
   // behaviour, which the compiler may use to assume every thread is active)
   const int t = tid - ji.t0, nt = act ? ji.nt : 64, n = act ? ji.n : 0;
   const DevCoef* cf = coefs + (act ? ji.inst : 0);
-  const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
+  // (the bounded kernels spend their vector registers on the boundary rows)
+  const Relaxer<Q, D, P, T, A, !B> relax = make_relaxer<Q, D, P, T, A, !B>(cf);
   // interior odd sweeps give threads r..nt-1 one node less, r = (n - 2H) mod nt
   const int r = act ? (n - 2 * H) % nt : 0;
   const int seam0 = (r > 0 && r + 2 * H <= nt) ? r : 0;
@@ -324,9 +345,9 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
   for (int s = 0; s < steps; ++s) {
     if (act) {
       if ((s & 1) == 0) {
-        aa_sweep_uniform<Q, false>(S, t, ne, t < re, nt, relax);
+        aa_sweep_range<Q, D, P, A, false>(S, 0, n, t, nt, ne, t < re, relax);
       } else {
-        aa_sweep_uniform<Q, true>(S, H + t, no, t < r, nt, relax);   // interior: no wrap
+        aa_sweep_range<Q, D, P, A, true>(S, H, n - H, t, nt, no, t < r, relax);   // interior: no wrap
         // the 2H seam nodes go to threads with one interior node less
         const int u = t - seam0;
         if (u >= 0 && u < 2 * H) aa_odd_wrap<Q>(S, u < H ? u : n - 2 * H + u, n, relax);
@@ -592,20 +613,30 @@ __device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const D
   const int n = ti.n, stride = ti.stride;
   const int W = sl.core + 2 * halo;
   const int strip = Q * halo;   // values per strip
-  const Relaxer<Q, D, P, T, A> relax = make_relaxer<Q, D, P, T, A>(cf);
+  const Relaxer<Q, D, P, T, A, true> relax = make_relaxer<Q, D, P, T, A, true>(cf);
   for (int j = 0; j < Q; ++j)
     for (int i = t; i < W; i += B) S[i * lds_stride(Q) + j] = gin[(int64_t)j * stride + wrap_any(sl.x0 - halo + i, n)];
   if (t == 0) *bail = 0;
   __syncthreads();
+  // step k of a block sweeps [k H, W - k H): nodes per thread W / B at k = 0,
+  // then 2H nodes fewer per step (kept as a count and a remainder, no division)
+  const int iters0 = W / B, rem0 = W - iters0 * B;
   int done = 0, sb = 0;
   for (int blk = 0; done < ti.steps; ++blk) {
     sb = ti.steps - done < s_per ? ti.steps - done : s_per;
+    int iters = iters0, rem = rem0;
     for (int k = 0; k < sb; ++k) {
-      const int lo = k * H, hi = W - k * H;
+      if (k > 0) {
+        rem -= 2 * H;
+        while (rem < 0) {
+          rem += B;
+          --iters;
+        }
+      }
       if ((k & 1) == 0)
-        aa_sweep<Q, false, 1>(S, lo, hi, t, B, relax);
+        aa_sweep_range<Q, D, P, A, false>(S, k * H, W - k * H, t, B, iters, t < rem, relax);
       else
-        aa_sweep<Q, true, 1>(S, lo, hi, t, B, relax);
+        aa_sweep_range<Q, D, P, A, true>(S, k * H, W - k * H, t, B, iters, t < rem, relax);
       __syncthreads();
     }
     done += sb;
