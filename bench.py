@@ -426,7 +426,7 @@ def main():
 
     def next_rows():
         out = {}
-        # bounded (Sec. IV boundaries) x tau sweep: Table VIII to t = 150 at 64 taus
+        # bounded (Sec. IV boundaries) x tau sweep: Table VIII to t = 150 at 256 taus
         p0, x, ex = W.table8_bounded()
         steps, layers = 15000, 2
         xb = np.concatenate([x[:layers], x[-layers:]])

@@ -173,7 +173,10 @@ __device__ __forceinline__ double int_pow(double x, int k) {
   return r;
 }
 
-// V: the kernel has vector registers to spare for kNV > 1 (see below)
+// V: the kernel's registers are spent on the node loop (the periodic resident
+// and slab kernels): coefficients are then pinned to registers as below.
+// Kernels that keep other state live across the loop (the bounded resident
+// kernels, the tiles that serve every variant) read them from the table.
 template <int Q, int D, int P, typename T, typename A, bool V = false>
 struct Relaxer {
   static constexpr int K = P == 0 ? D + 1 : (D + 1) / 2;   // coefficients per population
@@ -181,7 +184,7 @@ struct Relaxer {
   // the lower coefficients are held in scalar registers when they fit, so that
   // every code path of a kernel (the node loop, a masked or wrapped node) reads
   // the same registers instead of reloading the table
-  static constexpr bool kPin = P < 2 && Q * (K - 1) * (int)sizeof(A) / 4 <= 52;
+  static constexpr bool kPin = V && P < 2 && Q * (K - 1) * (int)sizeof(A) / 4 <= 52;
   // Larger tables keep their highest kNV coefficients per population in vector
   // registers, enough that the rest (read as scalar operands) leave the kernel
   // scalar registers for its own state: otherwise the node loop's operands

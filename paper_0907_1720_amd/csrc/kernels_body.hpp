@@ -253,19 +253,21 @@ __device__ __forceinline__ void aa_sweep_uniform(T* __restrict__ S, int x, int i
 
 // Sweep of [lo, hi) (lo + t, lo + t + B, ...) with the loop that suits the
 // variant: the uniform loop when the equilibrium's coefficients sit in scalar
-// registers or the power-sum body reads them once per node (there the masked
-// last pass costs nothing), else the per-lane loop -- a masked node body that
-// must reload a large table spends more than the loop control it saves.
+// registers, or for the two-class power sums with FP32 storage and FP64
+// relaxation (measured faster there; with FP64 storage the same loop spills
+// vector registers and is slower), else the per-lane loop -- a masked node
+// body that must reload a large table spends more than the loop control it
+// saves.
 // `iters` and `extra` describe [lo, hi) as in aa_sweep_uniform.
-template <int Q, int D, int P, typename T, typename A>
+template <int Q, int D, int P, typename T, typename A, bool V>
 constexpr bool uniform_sweep() {
-  return Relaxer<Q, D, P, T, A>::kPin || P == 3;   // (kPin does not depend on V)
+  return V && (Relaxer<Q, D, P, T, A, V>::kPin || (P == 3 && sizeof(T) == 4 && sizeof(A) == 8));
 }
 
-template <int Q, int D, int P, typename A, bool ODD, typename T, typename R>
+template <int Q, int D, int P, typename A, bool V, bool ODD, typename T, typename R>
 __device__ __forceinline__ void aa_sweep_range(T* __restrict__ S, int lo, int hi, int t, int B, int iters, bool extra,
                                                const R& r) {
-  if constexpr (uniform_sweep<Q, D, P, T, A>())
+  if constexpr (uniform_sweep<Q, D, P, T, A, V>())
     aa_sweep_uniform<Q, ODD>(S, lo + t, iters, extra, B, r);
   else
     aa_sweep<Q, ODD, 1>(S, lo, hi, t, B, r);
@@ -282,19 +284,25 @@ __device__ __forceinline__ double poly_init(const double* __restrict__ c, double
   return acc;
 }
 
+// exact solution at boundary node b (< 2 layers, left layers first) after step `step`
+__device__ __forceinline__ double bound_row(const DevJobInst& ji, int b, int step) {
+  return reinterpret_cast<const double*>(ji.phib)[(size_t)step * 2 * ji.layers + b];
+}
+
 // One population of one boundary node of a bounded instance in LDS after a
 // step, with the arithmetic of k_bound (boundary node b < 2 layers, left layers
 // first).  `odd`: an odd number of steps of this chunk is done, so f_j(x) =
 // S[x - e_j][opp(j)]; else S holds the natural layout.  Reads touch only the
 // first interior node, writes only boundary slots, so all (b, j) run at once.
+// `pb`: the exact solution at the node; `row`: the population's initialisation
+// polynomial (cf->init[j], or a copy of it in registers).
 template <int Q, int D, typename T>
-__device__ __forceinline__ void aa_bound_reset(T* __restrict__ S, const DevJobInst& ji, int b, int j, int step,
-                                            bool odd, const DevCoef* __restrict__ cf) {
+__device__ __forceinline__ void aa_bound_reset(T* __restrict__ S, const DevJobInst& ji, int b, int j, double pb,
+                                            bool odd, const DevCoef* __restrict__ cf, const double* __restrict__ row) {
   const int nl = ji.layers, n = ji.n;
   const bool left = b < nl;
   const int x = left ? b : n - 2 * nl + b;
   const int inner = left ? nl : n - 1 - nl;
-  const double pb = reinterpret_cast<const double*>(ji.phib)[(size_t)step * 2 * nl + b];
   auto at = [&](int y, int k) -> int { return odd ? wrapn(y - velocity<Q>(k), n) * lds_stride(Q) + opposite<Q>(k) : y * lds_stride(Q) + k; };
   double neq = 0.0;
   if (ji.bkind == 2) {
@@ -305,9 +313,9 @@ __device__ __forceinline__ void aa_bound_reset(T* __restrict__ S, const DevJobIn
       s += g;
       if (k == j) gj = g;
     }
-    neq = gj - (cf->gF > 0 ? general_stored_eq(cf, j, s + cf->phi_rest) : poly_init<D>(cf->init[j], s));
+    neq = gj - (cf->gF > 0 ? general_stored_eq(cf, j, s + cf->phi_rest) : poly_init<D>(row, s));
   }
-  const double eq = cf->gF > 0 ? general_stored_eq(cf, j, pb) : poly_init<D>(cf->init[j], pb - cf->phi_rest);
+  const double eq = cf->gF > 0 ? general_stored_eq(cf, j, pb) : poly_init<D>(row, pb - cf->phi_rest);
   S[at(x, j)] = (T)(eq + neq);
 }
 
@@ -342,12 +350,26 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
     for (int j = 0; j < Q; ++j)
       for (int x = t; x < n; x += nt) S[x * lds_stride(Q) + j] = g[(int64_t)j * ji.stride + x];
   __syncthreads();
+  // bounded jobs: the (node, population) a thread resets first keeps its
+  // equilibrium row in registers for the chunk, and each step's boundary value
+  // is loaded before the sweep, so that the reset after the barrier waits on
+  // no memory but LDS
+  const bool resets = B && act && ji.bkind != 0 && t < 2 * ji.layers * Q;
+  double row[B ? D + 1 : 1];
+  if constexpr (B) {
+#pragma unroll
+    for (int d = 0; d <= D; ++d) row[d] = resets ? cf->init[t % Q][d] : 0.0;
+  }
   for (int s = 0; s < steps; ++s) {
+    double pb_first = 0.0;
+    if constexpr (B) {
+      if (resets) pb_first = bound_row(ji, t / Q, s0 + s);
+    }
     if (act) {
       if ((s & 1) == 0) {
-        aa_sweep_range<Q, D, P, A, false>(S, 0, n, t, nt, ne, t < re, relax);
+        aa_sweep_range<Q, D, P, A, !B, false>(S, 0, n, t, nt, ne, t < re, relax);
       } else {
-        aa_sweep_range<Q, D, P, A, true>(S, H, n - H, t, nt, no, t < r, relax);   // interior: no wrap
+        aa_sweep_range<Q, D, P, A, !B, true>(S, H, n - H, t, nt, no, t < r, relax);   // interior: no wrap
         // the 2H seam nodes go to threads with one interior node less
         const int u = t - seam0;
         if (u >= 0 && u < 2 * H) aa_odd_wrap<Q>(S, u < H ? u : n - 2 * H + u, n, relax);
@@ -355,8 +377,13 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
     }
     __syncthreads();
     if constexpr (B) {
-      if (act && ji.bkind != 0)
-        for (int u = t; u < 2 * ji.layers * Q; u += nt) aa_bound_reset<Q, D, T>(S, ji, u / Q, u % Q, s0 + s, (s & 1) == 0, cf);
+      if (resets) {
+        aa_bound_reset<Q, D, T>(S, ji, t / Q, t % Q, pb_first, (s & 1) == 0, cf, row);
+        // (more than one (node, population) per thread: rows from the table)
+        for (int u = t + nt; u < 2 * ji.layers * Q; u += nt)
+          aa_bound_reset<Q, D, T>(S, ji, u / Q, u % Q, bound_row(ji, u / Q, s0 + s), (s & 1) == 0, cf,
+                                  cf->init[u % Q]);
+      }
       __syncthreads();
     }
   }
@@ -395,18 +422,21 @@ __device__ void resident_job(T* __restrict__ L, int steps, int s0, const DevJobI
 // variant, so that each runs at its own register count and occupancy: the
 // light variants (one node per iteration fits 64 VGPRs without spilling) are
 // compiled for eight waves per SIMD, the others without a bound.
-template <int Q, int D, int P, typename A>
+template <int Q, int D, int P, typename A, typename T = A>
 constexpr int resident_waves_per_simd() {
   if constexpr (P == 2) return 1;
-  if constexpr (P == 3) return 8;
+  // (the two-class power sums with FP32 storage: four waves, whose registers
+  // hold the conversions without spilling, ran faster than eight)
+  if constexpr (P == 3) return sizeof(T) == 4 && sizeof(A) == 8 ? 4 : 8;
   if constexpr (sizeof(A) == 4) return 8;
   if constexpr (Q <= 5) return (P ? D <= 9 : D <= 5) ? 8 : 1;
   return 1;
 }
 
-// (bounded kernels carry the boundary arithmetic and run unbounded in registers)
+// (bounded kernels carry the boundary arithmetic: workgroups of at most 512
+// threads, so that their registers hold it without spilling)
 template <int Q, int D, int P, typename T, typename A, bool B>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(B ? 1 : resident_waves_per_simd<Q, D, P, A>())))
+__global__ __launch_bounds__(B ? 512 : 1024) __attribute__((amdgpu_waves_per_eu(B ? 1 : resident_waves_per_simd<Q, D, P, A, T>())))
 void k_resident(const DevJob* __restrict__ jobs, const DevJobInst* __restrict__ jinst,
                                                    int njobs, int nchunks, int* __restrict__ counter,
                                                    int* __restrict__ slots, int* __restrict__ done,
@@ -634,9 +664,9 @@ __device__ void slab_instance(T* __restrict__ S, int* __restrict__ bail, const D
         }
       }
       if ((k & 1) == 0)
-        aa_sweep_range<Q, D, P, A, false>(S, k * H, W - k * H, t, B, iters, t < rem, relax);
+        aa_sweep_range<Q, D, P, A, true, false>(S, k * H, W - k * H, t, B, iters, t < rem, relax);
       else
-        aa_sweep_range<Q, D, P, A, true>(S, k * H, W - k * H, t, B, iters, t < rem, relax);
+        aa_sweep_range<Q, D, P, A, true, true>(S, k * H, W - k * H, t, B, iters, t < rem, relax);
       __syncthreads();
     }
     done += sb;

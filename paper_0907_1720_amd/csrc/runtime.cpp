@@ -639,7 +639,8 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int vgprs = std::max(1, resident_vgprs(q, pr, code));
       const int cu_waves = 4 * std::max(1, std::min(8, 512 / vgprs));
       const int jobs_per_cu = std::max<int>(1, (int)(b->lim.lds_max / cap));
-      const int kJobWaves = std::max(1, std::min(16, cu_waves / jobs_per_cu));
+      // (bounded kernels are compiled for workgroups of at most 512 threads)
+      const int kJobWaves = std::max(1, std::min(bnd ? 8 : 16, cu_waves / jobs_per_cu));
       // a pass that leaves most CUs idle (latency regime) gives every instance a
       // job of its own and up to a wave per 64 nodes: its steps end sooner
       const int kNodesPerWave = latency ? 64 : 128;
@@ -783,18 +784,20 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int halo = sp * H;
       const int cmax = W - 2 * halo;
       // two or more nodes per thread; if the kernel's registers do not let
-      // `wgs` workgroups of that size share a CU (its LDS is cut for wgs), halve
-      // the workgroup until they do, so no part of the LDS stays unused
+      // `wgs` workgroups of that size share a CU (its LDS is cut for wgs), take
+      // the largest smaller workgroup (a multiple of one wave, not below 256
+      // threads) that lets them, so no part of the LDS stays unused
       int block = std::min(1024, std::max(64, (W / 2 + 63) / 64 * 64));
       const size_t lds = (size_t)W * lds_stride(q) * es + 16;
       int per_cu = 0;
       if (cmax < halo || slab_occupancy(q, pr, code, block, lds, &per_cu) != hipSuccess) per_cu = 0;
-      while (per_cu > 0 && per_cu < wgs && block > 256) {
+      for (int nb = block - 64; per_cu > 0 && per_cu < wgs && nb >= 256; nb -= 64) {
         int pc = 0;
-        const int nb = (block / 2 + 63) / 64 * 64;
-        if (slab_occupancy(q, pr, code, nb, lds, &pc) != hipSuccess || pc <= per_cu) break;
-        block = nb;
-        per_cu = pc;
+        if (slab_occupancy(q, pr, code, nb, lds, &pc) != hipSuccess) break;
+        if (pc > per_cu) {
+          block = nb;
+          per_cu = pc;
+        }
       }
       const int capacity = std::min(per_cu * b->lim.cus, kMaxSlabs);
       if (per_cu > 0) min_per_cu = std::min(min_per_cu, per_cu);
