@@ -22,11 +22,13 @@ Reported:
   hbm_stream            the fused collide+stream path on a 2^25-node grid:
                         algorithmic HBM GB/s against 8 TB/s and a device copy
   ks_batches            the 1024-run Kuramoto-Sivashinsky batches at N = 1024,
-                        4096, 8192 to t = 20, FP64 and FP32, device time; FP32
+                        4096, 8192 to t = 20, FP64 and FP32, device time after
+                        the autotuner has timed planner settings on a copy; FP32
                         error against FP64 on every run and both against the
                         stored oracle references
-  kawahara_k22_batch    the 512-instance Kawahara + K(2,2) batch for 5000 steps,
-                        the same measurements plus the closed-form errors
+  kawahara_k22_batch    the 512-instance Kawahara + K(2,2) batch for 5000 steps
+                        (autotuned likewise), the same measurements plus the
+                        closed-form errors
   serving               a sweep of Poisson arrival rates of mixed solve requests
                         through the continuous-batching server (non-blocking
                         rounds): p50/p99 latency, queue wait and node updates/s
@@ -34,7 +36,7 @@ Reported:
                         against solo solves and FP32 ones against FP64
   autotune              the planner settings the autotuner kept for each batch
   next_rows             the extensions beyond the periodic batch, each timed on the
-                        device: the bounded Table VIII example as a 64-tau sweep
+                        device: the bounded Table VIII example as a 256-tau sweep
                         in one batch (resident, boundary layers reset in LDS) and
                         on the per-step streaming path; real-power equilibria;
                         the D1Q4 / D1Q6 lattices
@@ -313,6 +315,8 @@ def main():
                 steps = insts[0].steps
                 b = lbm.Batch([x.problem for x in insts], stream=stream.cuda_stream)
                 b.load_phi([x.phi0 for x in insts])
+                # planner settings timed on a copy of the batch (1000-step probes)
+                tuning = None if args.no_autotune else b.autotune(1000)
                 torch.cuda.synchronize()
                 b.advance(steps)
                 ms = b.last_advance_ms()
@@ -322,6 +326,7 @@ def main():
                 tot_nu[prec] += nu
                 tot_ms[prec] += ms
                 res[tag] = {"steps": steps, "kernel_ms": ms, "node_updates_per_s": nu / (ms * 1e-3), "status_ok": ok,
+                            "autotune": tuning,
                             "vs_oracle_inst0_t20": vs_gold(phis[0], f"ks_n{n}_i0_t20"),
                             "vs_oracle_inst1023_t20": vs_gold(phis[1023], f"ks_n{n}_i1023_t20")}
                 res[tag + "_phis"] = phis
@@ -342,6 +347,7 @@ def main():
             insts[tag] = xs
             b = lbm.Batch([x.problem for x in xs], stream=stream.cuda_stream)
             b.load_phi([x.phi0 for x in xs])
+            tuning = None if args.no_autotune else b.autotune(1000)
             b.advance(16)                  # warm-up (planner tables, code objects)
             b.load_phi([x.phi0 for x in xs])
             torch.cuda.synchronize()
@@ -356,7 +362,7 @@ def main():
                 ops += sum(y.problem.n for y in xs if y.problem.name == name) * 5000 * \
                     algorithmic_ops_per_nu(lbm.coefficients(x.problem))
             out[tag] = {"kernel_ms": ms, "node_updates_per_s": nu / (ms * 1e-3), "status_ok": ok,
-                        "alu_ops_frac": ops / (ms * 1e-3) / 1e12 / PEAK_VALU_TOPS,
+                        "alu_ops_frac": ops / (ms * 1e-3) / 1e12 / PEAK_VALU_TOPS, "autotune": tuning,
                         "vs_oracle": [vs_gold(phis[tag][i], f"c4_i{i}") for i in range(4)],
                         "vs_closed_form_rel2": [float(np.linalg.norm(phis[tag][i] - xs[i].exact(5000 * xs[i].problem.dt))
                                                       / np.linalg.norm(xs[i].exact(5000 * xs[i].problem.dt)))

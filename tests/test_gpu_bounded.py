@@ -168,6 +168,27 @@ def test_bounded_resident_bitwise_equals_streaming(key, prec):
         assert np.array_equal(a, b), steps
 
 
+@pytest.mark.parametrize("key", ["table_VIII_s1", "table_I_c10", "table_IV_q7_c10"])
+def test_bounded_resident_many_layers_bitwise_equals_streaming(key):
+    """32 reset layers at each end: more (node, population) pairs than an
+    instance has threads, so the resident kernel resets the pairs beyond each
+    thread's first from the coefficient table (its first pair from registers)."""
+    t, p, x, ex, kind = _table_problem(key)
+    p = dataclasses.replace(p, bc=KIND[kind])
+    layers = 32
+    for steps in (1, 2, 41):
+        say("case bounded many layers", key, steps)
+        out = []
+        for path in (lbm.PATH_STREAM, lbm.PATH_RESIDENT):
+            s = lbm.Solver(p)
+            s.set_path(path)
+            s.load_phi(ex(x, 0.0))
+            s.advance_bounded(_boundary_values(x, ex, p.dt, 0, steps, layers))
+            out.append(s.read_phi())
+            s.close()
+        assert np.array_equal(out[0], out[1]), steps
+
+
 def test_bounded_batch_with_forced_chunks_and_periodic_neighbours():
     """Several bounded instances and periodic ones in one batch, the steps split
     into chunks (each chunk reads its own boundary rows): every result equals
