@@ -36,6 +36,15 @@ def say(*a):
     print(*a, flush=True)
 
 
+def maxerr(a, b):
+    """The relative L2 error, or half the largest element error relative to
+    max |b| where that is larger: a tolerance `tol` on it bounds the L2 error by
+    tol and every element by 2 tol (a rounding-driven difference peaks at up to
+    about twice its L2 size; 1.6x measured here)."""
+    return max(float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+               0.5 * float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+
+
 def rel2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
@@ -79,7 +88,7 @@ def test_bounded_matches_oracle(key, steps):
     got, t, p, x, ex, kind = gpu_bounded(key, reports)
     want = O.run_bounded(dataclasses.replace(p, bc=0), x, ex, steps, kind, report=reports)
     for r in reports:
-        err = rel2(got[r], want[r])
+        err = maxerr(got[r], want[r])
         say("  ", key, r, f"{err:.2e}")
         assert err <= 1e-12, (key, r, err)
 
@@ -115,7 +124,7 @@ def test_bounded_table_iv_needs_corrected_aux_moments():
 def test_bounded_fp32_deviation_storage(key):
     got64, t, p, x, ex, kind = gpu_bounded(key, [300])
     got32, *_ = gpu_bounded(key, [300], prec=W.F32_DEV)
-    err = rel2(got32[300], got64[300])
+    err = maxerr(got32[300], got64[300])
     say("  fp32 bounded", key, f"{err:.2e}")
     assert err <= 1e-4
 
@@ -248,7 +257,7 @@ def test_bounded_tau_sweep_in_one_batch():
     # the oracle at two of the taus
     for k in (3, 6):
         want = O.run_bounded(dataclasses.replace(p, bc=0, tau=taus[k]), x, ex, steps, kind, report=[steps])[steps]
-        assert rel2(out["phi"][k], want) <= 1e-12
+        assert maxerr(out["phi"][k], want) <= 1e-12
     say("  tau sweep E", [f"{e:.3g}" for e in out["E"]], "tau_opt", out["tau_opt"])
     assert out["tau_opt"] == 0.97                         # the paper's choice: the stable edge
     # the paper's printed E at t = 10 for its tau

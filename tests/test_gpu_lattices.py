@@ -9,7 +9,8 @@ step for the settings below; the oracle's own result moves by <= 3e-14 when
 phi0 changes by 1e-15) keeps the FP64 comparison meaningful.  The diffusive
 third- and fifth-order equations below are stable on them and are compared
 over hundreds of steps.  Every kernel path must agree bitwise with the HBM
-streaming step; FP64 agrees with the oracle to relative L2 <= 1e-12, the FP32
+streaming step; FP64 agrees with the oracle to 1e-12 in relative L2 (every
+element to 2e-12 of max |phi|), the FP32
 deviation storage to 1e-4 (stable cases: about 400 steps of ~6e-8 relative
 rounding on populations of the size of phi's deviation).
 """
@@ -42,6 +43,15 @@ def _gpu():
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def maxerr(a, b):
+    """The relative L2 error, or half the largest element error relative to
+    max |b| where that is larger: a tolerance `tol` on it bounds the L2 error by
+    tol and every element by 2 tol (a rounding-driven difference peaks at up to
+    about twice its L2 size; 1.6x measured here)."""
+    return max(float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+               0.5 * float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
 
 
 def rel2(a, b):
@@ -109,7 +119,7 @@ def test_even_lattice_fp64_all_paths(name, n):
             continue
         tiling = (8, 8) if path == lbm.PATH_SLAB else (0, 0)
         got = _run(p, phi0, steps, path, tiling)
-        err = rel2(got, want)
+        err = maxerr(got, want)
         say("  path", path, f"{err:.2e}")
         assert err <= FP64_TOL, path
         if ref is None:
@@ -127,7 +137,7 @@ def test_even_lattice_fp32(name, prec):
     want = O.run(dataclasses.replace(p, prec=W.F64), phi0, steps)
     outs = [_run(p, phi0, steps, path, (8, 8) if path == lbm.PATH_SLAB else (0, 0))
             for path in (lbm.PATH_STREAM, lbm.PATH_RESIDENT, lbm.PATH_SLAB)]
-    err = rel2(outs[0], want)
+    err = maxerr(outs[0], want)
     say("case lattice fp32", name, prec, f"{err:.2e}")
     assert err <= FP32_TOL
     for o in outs[1:]:
@@ -160,7 +170,7 @@ def test_mixed_lattice_batch_equals_single_solves():
         say("case mixed", i, p.lattice(), p.n)
         assert np.array_equal(g, ref), i
         if p.n <= 1000:
-            assert rel2(g, O.run(p, phi0, steps)) <= FP64_TOL
+            assert maxerr(g, O.run(p, phi0, steps)) <= FP64_TOL
 
 
 @pytest.mark.parametrize("kind", ["eq", "nee"])
@@ -184,6 +194,6 @@ def test_even_lattice_bounded_matches_oracle(kind):
     s.advance_bounded(np.stack([ex(xb, k * p.dt) for k in range(1, steps + 1)]), layers)
     got = s.read_phi()
     s.close()
-    err = rel2(got, want)
+    err = maxerr(got, want)
     say("case lattice bounded", kind, f"{err:.2e}")
     assert err <= FP64_TOL

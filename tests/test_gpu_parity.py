@@ -1,8 +1,9 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle.
 
-FP64 results must agree with the oracle to relative L2 <= 1e-12; the FP32
-deviation storage to the tolerance stated per workload (1e-4 for the
-soliton/compacton batches, 1e-3 for Kuramoto-Sivashinsky).  Kernel paths
+FP64 results must agree with the oracle to 1e-12 in relative L2 (and every
+element to 2e-12 of max |phi|); the FP32 deviation storage to the tolerance
+stated per workload (1e-4 for the soliton/compacton batches, 1e-3 for
+Kuramoto-Sivashinsky; elements to twice that).  Kernel paths
 (HBM streaming, LDS resident, batched) must agree bitwise with each other.
 """
 import dataclasses
@@ -34,6 +35,15 @@ def _gpu():
     yield
 
 
+def maxerr(a, b):
+    """The relative L2 error, or half the largest element error relative to
+    max |b| where that is larger: a tolerance `tol` on it bounds the L2 error by
+    tol and every element by 2 tol (a rounding-driven difference peaks at up to
+    about twice its L2 size; 1.6x measured here)."""
+    return max(float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+               0.5 * float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+
+
 def rel2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
@@ -62,7 +72,7 @@ def test_config1_kdv_fp64_matches_oracle():
     say("case config1a", inst.problem.n, inst.steps)
     want = O.run(inst.problem, inst.phi0, inst.steps)
     got = gpu_run(inst.problem, inst.phi0, inst.steps)
-    assert rel2(got, want) <= FP64_TOL
+    assert maxerr(got, want) <= FP64_TOL
     # and the travelling soliton it approximates (the oracle's own error)
     assert abs(rel2(got, inst.exact(inst.steps * inst.problem.dt)) - rel2(want, inst.exact(2.0))) < 1e-9
 
@@ -76,7 +86,7 @@ def test_kernel_paths_bitwise_identical(steps):
     assert np.array_equal(a, b)
     if steps <= 2:
         want = O.run(inst.problem, inst.phi0, steps)
-        assert rel2(a, want) <= FP64_TOL
+        assert maxerr(a, want) <= FP64_TOL
 
 
 # ---------------------------------------------------------------------------
@@ -108,7 +118,7 @@ def test_ragged_sizes(n, kind):
         paths.append(lbm.PATH_RESIDENT)
     for path in paths:
         got = gpu_run(p, phi0, steps, path)
-        assert rel2(got, want) <= FP64_TOL, path
+        assert maxerr(got, want) <= FP64_TOL, path
 
 
 @pytest.mark.parametrize("n,steps,s_per", [(257, 37, 8), (1000, 64, 16), (4099, 45, 32), (64, 9, 4), (5, 7, 2)])
@@ -137,7 +147,7 @@ def test_tiled_path_bitwise_equals_resident_and_stream(n, steps, s_per, kind):
         s.close()
     for path, v in outs.items():
         assert np.array_equal(v, outs[lbm.PATH_STREAM]), path
-    assert rel2(outs[lbm.PATH_TILED], O.run(p, phi0, steps)) <= FP64_TOL
+    assert maxerr(outs[lbm.PATH_TILED], O.run(p, phi0, steps)) <= FP64_TOL
 
 
 # slab path: (n, steps, steps per halo exchange, workgroups per CU) chosen for 1, 2, 3, 10
@@ -166,7 +176,7 @@ def test_slab_path_bitwise_equals_stream(n, steps, s_per, wgs, kind):
         s.close()
     assert np.array_equal(outs[lbm.PATH_SLAB], outs[lbm.PATH_STREAM])
     if kind != "kdv32":
-        assert rel2(outs[lbm.PATH_SLAB], O.run(p, phi0, 2 * steps + 1)) <= FP64_TOL
+        assert maxerr(outs[lbm.PATH_SLAB], O.run(p, phi0, 2 * steps + 1)) <= FP64_TOL
 
 
 def test_slab_path_several_cooperative_launches():
@@ -247,7 +257,7 @@ def test_config2_batch_matches_oracle(prec, tol, cons):
         got, st = b.read_phi(k)
         assert st == lbm.OK
         want = O.run(dataclasses.replace(insts[k].problem, prec=W.F64), insts[k].phi0, steps)
-        err = rel2(got, want)
+        err = maxerr(got, want)
         say("  inst", k, insts[k].problem.name, insts[k].problem.n, f"{err:.2e}")
         assert err <= tol, (k, err)
         # Sum of phi is conserved
@@ -284,7 +294,7 @@ def test_config2_full_size_as_benchmarked(prec, tol, cons):
         worst = max(worst, drift)
         if k in sample:
             want = O.run(dataclasses.replace(insts[k].problem, prec=W.F64), insts[k].phi0, steps)
-            err = rel2(got, want)
+            err = maxerr(got, want)
             say("  inst", k, names[k], ns[k], f"{err:.2e}")
             assert err <= tol, (k, err)
     b.close()
@@ -423,7 +433,7 @@ def test_large_instances_batch_tiled_matches_oracle():
     for k, inst in enumerate(insts):
         got, st = b.read_phi(k)
         assert st == lbm.OK
-        assert rel2(got, O.run(inst.problem, inst.phi0, steps[k])) <= FP64_TOL, k
+        assert maxerr(got, O.run(inst.problem, inst.phi0, steps[k])) <= FP64_TOL, k
     b.close()
 
 
@@ -435,9 +445,9 @@ def test_config3_ks_sample(n):
     say("case config3", n, steps)
     want = O.run(i64.problem, i64.phi0, steps)
     got = gpu_run(i64.problem, i64.phi0, steps)
-    assert rel2(got, want) <= FP64_TOL
+    assert maxerr(got, want) <= FP64_TOL
     got32 = gpu_run(i32.problem, i32.phi0, steps)
-    assert rel2(got32, want) <= FP32_TOL_KS
+    assert maxerr(got32, want) <= FP32_TOL_KS
 
 
 # ---------------------------------------------------------------------------
@@ -451,10 +461,10 @@ def test_config4_sample(i):
     say("case config4", inst.problem.name, inst.problem.n, steps)
     want = O.run(inst.problem, inst.phi0, steps)
     got = gpu_run(inst.problem, inst.phi0, steps)
-    assert rel2(got, want) <= FP64_TOL
+    assert maxerr(got, want) <= FP64_TOL
     p32 = dataclasses.replace(inst.problem, prec=W.F32_DEV)
     got32 = gpu_run(p32, inst.phi0, steps)
-    assert rel2(got32, want) <= FP32_TOL
+    assert maxerr(got32, want) <= FP32_TOL
 
 
 @pytest.mark.parametrize("which", ["ks8192", "kawahara_k22"])
@@ -479,7 +489,7 @@ def test_large_grid_batches_as_benchmarked(which):
         assert st == lbm.OK, k
         if k in sample:
             want = O.run(insts[k].problem, insts[k].phi0, steps + 16)
-            err = rel2(got, want)
+            err = maxerr(got, want)
             say("  inst", k, insts[k].problem.name, insts[k].problem.n, f"{err:.2e}")
             assert err <= FP64_TOL, (k, err)
     b.close()
@@ -493,7 +503,7 @@ def test_random_sixth_order_equation():
     want = O.run(p, phi0, 200)
     for path in (lbm.PATH_STREAM, lbm.PATH_RESIDENT):
         got = gpu_run(p, phi0, 200, path)
-        assert rel2(got, want) <= FP64_TOL
+        assert maxerr(got, want) <= FP64_TOL
 
 
 # ---------------------------------------------------------------------------
@@ -548,7 +558,7 @@ def test_nonfinite_is_isolated_to_its_instance():
     g2, st2 = b.read_phi(2)
     assert st0 == lbm.OK and st2 == lbm.OK
     assert np.array_equal(g0, g2)
-    assert rel2(g0, O.run(good.problem, good.phi0, 500)) <= FP64_TOL
+    assert maxerr(g0, O.run(good.problem, good.phi0, 500)) <= FP64_TOL
     b.close()
 
 
@@ -581,5 +591,5 @@ def test_caller_owned_device_memory_and_device_phi():
     s.read_phi(out)
     torch.cuda.synchronize()
     want = O.run(inst.problem, inst.phi0, 500)
-    assert rel2(out.cpu().numpy(), want) <= FP64_TOL
+    assert maxerr(out.cpu().numpy(), want) <= FP64_TOL
     s.close()

@@ -7,7 +7,7 @@ part nu of the exponents -- square roots when every nu is 1/2, 1/4 or 3/4 (the
 n = 0.5, 1.5 cases below), exp2(nu log2 phi) otherwise (the n = 1/3 case); the
 oracle takes numpy powers of the exact binary exponents.  Both are accurate to
 about an ulp, so the
-FP64 bar stays relative L2 <= 1e-12; every kernel path evaluates the same
+FP64 bar stays 1e-12 in relative L2 (every element 2e-12 of max |phi|); every kernel path evaluates the same
 per-node function and must agree bitwise with the HBM streaming step.  FP32
 deviation storage: 1e-4 (as for the polynomial equilibria).
 """
@@ -40,6 +40,15 @@ def _gpu():
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def maxerr(a, b):
+    """The relative L2 error, or half the largest element error relative to
+    max |b| where that is larger: a tolerance `tol` on it bounds the L2 error by
+    tol and every element by 2 tol (a rounding-driven difference peaks at up to
+    about twice its L2 size; 1.6x measured here)."""
+    return max(float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+               0.5 * float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
 
 
 def rel2(a, b):
@@ -98,7 +107,7 @@ def test_power_sums_fp64_all_paths(name, n):
         if path == lbm.PATH_RESIDENT and (p.lattice() | 1) * n * 8 + 64 > 160 * 1024:
             continue
         got = _run(p, phi0, steps, path, (8, 8) if path == lbm.PATH_SLAB else (0, 0))
-        err = rel2(got, want)
+        err = maxerr(got, want)
         say("  path", path, f"{err:.2e}")
         assert err <= FP64_TOL, path
         if ref is None:
@@ -115,7 +124,7 @@ def test_power_sums_fp32(name):
     want = O.run(dataclasses.replace(p, prec=W.F64), phi0, steps)
     outs = [_run(p, phi0, steps, path, (8, 8) if path == lbm.PATH_SLAB else (0, 0))
             for path in (lbm.PATH_STREAM, lbm.PATH_RESIDENT, lbm.PATH_SLAB)]
-    err = rel2(outs[0], want)
+    err = maxerr(outs[0], want)
     say("case powers fp32", name, f"{err:.2e}")
     assert err <= FP32_TOL
     for o in outs[1:]:
@@ -194,7 +203,7 @@ def test_power_sums_bounded_matches_oracle(kind):
     s.advance_bounded(np.stack([ex(xb, k * p.dt) for k in range(1, steps + 1)]), layers)
     got = s.read_phi()
     s.close()
-    err = rel2(got, want)
+    err = maxerr(got, want)
     say("case powers bounded", kind, f"{err:.2e}")
     assert err <= FP64_TOL
 

@@ -32,6 +32,15 @@ def say(*a):
     print(*a, flush=True)
 
 
+def maxerr(a, b):
+    """The relative L2 error, or half the largest element error relative to
+    max |b| where that is larger: a tolerance `tol` on it bounds the L2 error by
+    tol and every element by 2 tol (a rounding-driven difference peaks at up to
+    about twice its L2 size; 1.6x measured here)."""
+    return max(float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+               0.5 * float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+
+
 def rel2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
@@ -101,7 +110,7 @@ def test_served_results_match_oracle():
         checked.add(key)
         want = O.run(dataclasses.replace(r.problem, prec=W.F64), r.phi0, r.steps)
         tol = 1e-12 if r.problem.prec == W.F64 else (1e-3 if r.problem.name == "ks" else 1e-4)
-        err = rel2(out["results"][k], want)
+        err = maxerr(out["results"][k], want)
         say("  ", r.problem.name, r.problem.prec, r.problem.n, r.steps, f"{err:.2e}")
         assert err <= tol, (k, r.problem.name, err)
 
@@ -177,7 +186,7 @@ def test_extension_models_served_alongside_the_mix():
             checked.add(key)
             want = O.run(dataclasses.replace(p, prec=W.F64), f, s)
             tol = 1e-12 if p.prec == W.F64 else 1e-4
-            err = rel2(phi, want)
+            err = maxerr(phi, want)
             say("    vs oracle", f"{err:.2e}")
             assert err <= tol, (k, p.name, err)
 

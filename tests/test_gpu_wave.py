@@ -5,8 +5,8 @@ The closed forms of the paper's bounded examples (Sec. IV; Tables I, II and
 IV-VIII) are written below in numpy from the same definitions the oracle's
 table pins use; the device rows must agree with them to a few ulps, and a
 bounded run fed by device rows must agree with the same run fed by host rows
-(relative L2 <= 1e-13: the rows differ by the last bits of exp/cosh/tanh) and
-with the CPU oracle (<= 1e-12).  Device rows are deterministic, so the
+(<= 1e-13 in relative L2, every element 2e-13 of max |phi|: the rows differ by
+the last bits of exp/cosh/tanh) and with the CPU oracle (<= 1e-12).  Device rows are deterministic, so the
 resident and streaming paths and batch vs single solves agree bit for bit.
 """
 import dataclasses
@@ -37,6 +37,15 @@ def _gpu():
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def maxerr(a, b):
+    """The relative L2 error, or half the largest element error relative to
+    max |b| where that is larger: a tolerance `tol` on it bounds the L2 error by
+    tol and every element by 2 tol (a rounding-driven difference peaks at up to
+    about twice its L2 size; 1.6x measured here)."""
+    return max(float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+               0.5 * float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
 
 
 def rel2(a, b):
@@ -130,9 +139,9 @@ def test_wave_run_matches_host_rows_and_oracle(key, steps):
     dev = s.read_phi()
     s.close()
     want = O.run_bounded(p, x, ex, steps, kind, layers=layers, report=[steps])[steps]
-    say("case wave run", key, f"{rel2(dev, host):.2e}", f"{rel2(dev, want):.2e}")
-    assert rel2(dev, host) <= 1e-13
-    assert rel2(dev, want) <= 1e-12
+    say("case wave run", key, f"{maxerr(dev, host):.2e}", f"{maxerr(dev, want):.2e}")
+    assert maxerr(dev, host) <= 1e-13
+    assert maxerr(dev, want) <= 1e-12
 
 
 def test_wave_paths_agree_bitwise_and_calls_continue():
