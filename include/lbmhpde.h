@@ -281,7 +281,13 @@ lbm_status lbm_batch_create(const lbm_desc* descs, int32_t count, void* stream, 
 lbm_status lbm_batch_load_phi(lbm_batch b, const double* const* phi0);
 
 /* Advance instance i by steps[i] (>= 0) steps, all instances in persistent
-   launches; asynchronous.  steps == NULL advances nothing. */
+   launches; asynchronous.  steps == NULL advances nothing.  The launches of
+   one call (one per lattice, precision and variant on each path) run side by
+   side on up to 16 internal streams forked from and joined back to the
+   batch's stream, as many as the hardware queues HIP gives the process
+   (GPU_MAX_HW_QUEUES, 4 by default; streams that share a queue run one after
+   another): launches in order of estimated duration, longest first, each to
+   the stream with the least estimated work so far. */
 lbm_status lbm_batch_advance(lbm_batch b, const int64_t* steps);
 /* Bounded instances of a batch (Sec. IV boundaries, as lbm_advance_bounded):
    every instance advances `steps` (<= 2^30) steps; bounded instance i resets
@@ -322,6 +328,13 @@ lbm_status lbm_batch_set_tiling(lbm_batch b, int32_t steps_per_launch, int32_t w
    A chunk reloads its job's state from HBM and writes it back, so results do
    not depend on either value (bitwise).  INVALID_ARG outside those ranges. */
 lbm_status lbm_batch_set_resident(lbm_batch b, int32_t max_workgroups, int32_t chunks);
+
+/* Streams the launches of one lbm_batch_advance are spread over: 0 =
+   automatic (the hardware queues HIP gives the process, GPU_MAX_HW_QUEUES,
+   at most 16), 1..16 = that many.  More streams than hardware queues only
+   chain launches behind each other; results do not depend on the value
+   (bitwise).  INVALID_ARG outside 0..16. */
+lbm_status lbm_batch_set_lanes(lbm_batch b, int32_t lanes);
 
 /* Autotuner result: the planner settings it kept (as set by lbm_batch_set_path,
    lbm_batch_set_tiling and lbm_batch_set_resident) and the measured rates. */

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -35,7 +36,7 @@ constexpr int kMaxSlabs = 2048;       // workgroups of one slab launch
 constexpr int kSplitNodes = 1024;     // smallest grid split into slabs when the GPU is mostly idle
 constexpr int kMaxResidentGrid = 256 * 8;
 constexpr int kMaxLaunches = 64;      // resident launches per advance pass (one per lattice, precision, variant)
-constexpr int kAuxStreams = 8;        // concurrent lanes (resident launches, tiled groups)
+constexpr int kAuxStreams = 16;       // concurrent lanes (resident launches, tiled groups, slab launches)
 constexpr uint64_t kMagic = 0x4c424d4850444531ull;   // "LBMHPDE1"
 
 struct HostInst {
@@ -143,6 +144,7 @@ struct lbm_batch_s {
   int tile_wgs = 0;                   // tiled workgroups per CU the LDS budget is split for (0 = automatic)
   int res_grid = 0;                   // cap on the resident grid (0 = automatic)
   int res_chunks = 0;                 // step chunks per resident job (0 = automatic)
+  int lanes = 0;                      // streams a pass spreads its launches over (0 = automatic)
   hipStream_t aux[kAuxStreams] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kAuxStreams] = {};
@@ -560,6 +562,20 @@ constexpr int64_t kMinChunkSteps = 256;
 constexpr int kMaxChunks = 64;
 constexpr int64_t kMinSlabChunk = 256;   // steps of one chunk of a slab launch
 
+// Lanes a pass spreads its launches over.  HIP runs a process's streams on
+// GPU_MAX_HW_QUEUES hardware queues (4 unless that variable is set) and new
+// streams go to the least used queue; kernels on streams that share a queue
+// run one after another, so more lanes than queues only chain launches
+// behind each other in creation order.
+int hw_lanes() {
+  static const int lanes = [] {
+    const char* v = std::getenv("GPU_MAX_HW_QUEUES");
+    const int n = v ? std::atoi(v) : 0;
+    return n > 0 ? std::min(n, kAuxStreams) : std::min(4, kAuxStreams);
+  }();
+  return lanes;
+}
+
 // One pass: every instance advances by steps[i] <= kMaxStepsPerLaunch.
 lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   const int count = (int)b->inst.size();
@@ -610,7 +626,8 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   LBM_HIP(hipEventSynchronize(b->items_done[k]));
   DevJobInst* hitems = b->items_host + (size_t)k * b->items_cap;
   DevJob* hjobs = b->jobs_host + (size_t)k * b->items_cap;
-  struct Launch { int q; int prec; int code; int first, count; size_t lds; int block; int64_t maxsteps; };
+  // est_max / est_sum: the longest job's and all jobs' duration estimates
+  struct Launch { int q; int prec; int code; int first, count; size_t lds; int block; int64_t maxsteps; double est_max, est_sum; };
   std::vector<Launch> launches;
   int used = 0, njobs = 0;
   constexpr int kMaxJobInstances = 16;   // instances per job (one wave each at least)
@@ -672,7 +689,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int slots = jobs_per_cu * b->lim.cus;
       if (!latency && (int)bins.size() < slots && (int)g.size() > (int)bins.size())
         pack(std::max(1, ((int)g.size() + slots - 1) / slots));
-      Launch L{q, pr, code, njobs, 0, 0, 64, 0};
+      Launch L{q, pr, code, njobs, 0, 0, 64, 0, 0.0, 0.0};
       struct Planned { const Bin* bin; std::vector<int> waves; double est; };
       std::vector<Planned> plan;
       for (const Bin& bn : bins) {
@@ -710,6 +727,8 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
         const std::vector<int>& wv = pl.waves;
         const int m = (int)bn.members.size();
         L.maxsteps = std::max<int64_t>(L.maxsteps, bn.steps);
+        L.est_max = std::max(L.est_max, pl.est);
+        L.est_sum += pl.est;
         DevJob& jb = hjobs[njobs++];
         jb.first = used;
         jb.count = m;
@@ -746,7 +765,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     }
   }
   // temporal blocking plan per (q, prec) group
-  struct TileGroup { int q; int prec; int first, ntiles, tfirst, tcount, s, halo, launches, block; size_t lds; };
+  struct TileGroup { int q; int prec; int first, ntiles, tfirst, tcount, s, halo, launches, block; size_t lds; double est; };
   std::vector<TileGroup> tgroups;
   std::vector<DevTile> tvec;
   // tile-instance records of this pass (the tiled path: one per instance; the
@@ -763,7 +782,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   // by part of a chunk (without chunks, a last launch with a few instances
   // costs a whole launch's time).  An instance's chunk c + 1 always lies in a
   // later launch than its chunk c, which the lane's order serialises.
-  struct SlabLaunch { int q; int prec; int code; int first, count, cap, s, halo, block; size_t lds; size_t xoff; int foff; };
+  struct SlabLaunch { int q; int prec; int code; int first, count, cap, s, halo, block; size_t lds; size_t xoff; int foff; double est; };
   std::vector<SlabLaunch> slaunch;
   std::vector<DevSlab> svec;
   size_t xbuf_need = 0;
@@ -801,7 +820,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       }
       const int capacity = std::min(per_cu * b->lim.cus, kMaxSlabs);
       if (per_cu > 0) min_per_cu = std::min(min_per_cu, per_cu);
-      SlabLaunch L{q, pr, code, (int)svec.size(), 0, capacity, sp, halo, block, lds, 0, 0};
+      SlabLaunch L{q, pr, code, (int)svec.size(), 0, capacity, sp, halo, block, lds, 0, 0, 0.0};
       // the instances that take slabs, their slab counts and core widths
       std::vector<std::pair<int, int>> mem;   // (instance, slabs)
       int64_t total = 0, maxsteps = 0;
@@ -858,7 +877,11 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
             slaunch.push_back(L);
             L.first = (int)svec.size();
             L.count = 0;
+            L.est = 0.0;
           }
+          // duration estimate, in the unit of the resident jobs' (steps x nodes
+          // of the busiest thread x arithmetic per node)
+          L.est = std::max(L.est, (double)st * ((core + 2 * halo + block - 1) / block) * (q * ((h.D & 0xff) + 3)));
           DevTileInst ti{};
           ti.off = h.off;
           ti.n = h.n;
@@ -971,9 +994,9 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       while (sp > 1 && (W - 2 * sp * H < 2 * sp * H || (b->tile_steps == 0 && 8 * sp * H > want))) sp /= 2;
       const int halo = sp * H;
       const int core = std::max(1, std::min(W - 2 * halo, want));
-      TileGroup G{q, pr, (int)tvec.size(), 0, tin_used, 0, sp, halo, 0, kBlock, 0};
+      TileGroup G{q, pr, (int)tvec.size(), 0, tin_used, 0, sp, halo, 0, kBlock, 0, 0.0};
       int64_t maxsteps = 0;
-      int maxcore = 1;
+      int maxcore = 1, maxd = 0;
       for (int i : g) {
         const HostInst& h = b->inst[i];
         htin.emplace_back();
@@ -991,6 +1014,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
           tvec.push_back(t);
         }
         maxcore = std::max(maxcore, c);
+        maxd = std::max(maxd, h.D & 0xff);
         maxsteps = std::max<int64_t>(maxsteps, steps[i]);
         ++tin_used;
       }
@@ -1000,6 +1024,10 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       G.lds = (size_t)lds_stride(q) * (maxcore + 2 * halo) * es;
       // two or more nodes per thread
       G.block = std::min(kBlock, std::max(64, ((maxcore + 2 * halo) / 2 + 63) / 64 * 64));
+      // duration estimate (as the resident jobs'): the launches' steps x nodes of
+      // the busiest thread x arithmetic per node x rounds of tiles over the CUs
+      G.est = (double)G.launches * sp * ((maxcore + 2 * halo + G.block - 1) / G.block) * (q * (maxd + 3)) *
+              ((G.ntiles + 2 * b->lim.cus - 1) / (2 * b->lim.cus));
       tgroups.push_back(G);
     }
   }
@@ -1067,88 +1095,123 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
     LBM_HIP(hipMemsetAsync(counters, 0, sizeof(int) * kMaxLaunches, b->stream));
     LBM_HIP(hipMemsetAsync(b->done + (size_t)k * b->items_cap, 0, sizeof(int) * njobs, b->stream));
   }
-  // every resident launch and every tiled group is a lane on an auxiliary
-  // stream; the fork is recorded after all table uploads above
-  const int lanes = (int)launches.size() + (int)tgroups.size() +
-                    (slaunch.empty() ? 0 : slab_side_by_side ? (int)slaunch.size() : 1);
-  const bool fork = lanes > 1;
-  if (fork) LBM_HIP(hipEventRecord(b->fork, b->stream));
-  int lane = 0;
-  auto lane_stream = [&](int l) -> hipStream_t { return fork ? b->aux[l % kAuxStreams] : b->stream; };
-  for (size_t l = 0; l < launches.size(); ++l, ++lane) {
-    const Launch& L = launches[l];
-    hipStream_t st = lane_stream(lane);
-    if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
-    int per_cu = 0;
-    LBM_HIP(resident_occupancy(L.q, L.prec, L.code, L.block, L.lds, &per_cu));
-    if (per_cu < 1) return LBM_ERR_UNSUPPORTED;
-    int grid = std::min<int>(std::min<int>(L.count, per_cu * b->lim.cus), kMaxResidentGrid);
-    if (b->res_grid > 0) grid = std::min(grid, b->res_grid);
-    // more jobs than workgroups: split the steps into chunks so that each
-    // workgroup takes about kChunkItems items and the launch ends evenly;
-    // chunks keep at least kMinChunkSteps steps (a chunk reloads its state)
-    int nchunks = 1;
-    if (L.count > grid) {
-      nchunks = (int)std::min<int64_t>((kChunkItems * (int64_t)grid + L.count - 1) / L.count,
-                                       std::max<int64_t>(1, L.maxsteps / kMinChunkSteps));
-      nchunks = std::max(1, std::min(nchunks, kMaxChunks));
-    }
-    if (b->res_chunks > 0) nchunks = b->res_chunks;
-    int* slots = b->slots + (size_t)(k * kMaxLaunches + l) * kMaxResidentGrid;
-    int* done = b->done + (size_t)k * b->items_cap + L.first;
-    const long long ticks = wait_ticks(b, L.maxsteps / nchunks + 1);
-    const int stall = (b->test_stall == 1 && l == 0 && nchunks > 1) ? 0 : -1;
-    LBM_HIP(launch_resident(L.q, L.prec, L.code, djobs + L.first, ditems, L.count, nchunks, counters + l, slots, done,
-                            b->coefs, b->status, ticks, stall, grid, L.block, L.lds, st));
-  }
-  for (const TileGroup& G : tgroups) {
-    hipStream_t st = lane_stream(lane);
-    if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
-    ++lane;
-    DevTile* dt = b->tiles + (size_t)k * b->tiles_cap + G.first;
-    DevTileInst* dti = b->tinsts + (size_t)k * b->tinsts_cap;
-    void* b0 = G.prec ? (void*)b->f32[0] : (void*)b->f64[0];
-    void* b1 = G.prec ? (void*)b->f32[1] : (void*)b->f64[1];
-    for (int l = 0; l < G.launches; ++l)
-      LBM_HIP(launch_tile(G.q, G.prec, dt, G.ntiles, dti, b0, b1, l, G.s, G.halo, b->coefs, b->status, G.block, G.lds,
-                          st));
-    for (int t = G.tfirst; t < G.tfirst + G.tcount; ++t) {
-      HostInst& h = b->inst[htin[t].inst];
-      const int L = (int)((htin[t].steps + G.s - 1) / G.s);
-      h.cur = htin[t].cur0 ^ (L & 1);
-    }
-  }
+  // Lanes: every resident launch, every tiled group and every slab launch (or
+  // the chain of slab launches, when they cannot run side by side) is one
+  // item; with more items than lanes, each item in order of its duration
+  // estimate, longest first, goes to the lane with the least estimated work
+  // so far (longest-processing-time scheduling).  With no more items than
+  // lanes each has a lane of its own, issued in plan order (launches that each
+  // fill the GPU take its CUs in that order: the 4096-instance KdV/mKdV pass
+  // ran 1% longer with the longer mKdV launch first).  The fork is recorded
+  // after all table uploads above.
   // slab launches: each needs all its workgroups resident at once.  Each fits
   // the GPU alone, and the other lanes' kernels never wait on it, so its
   // workgroups all get CUs once those kernels retire; two slab launches side
-  // by side could each hold CUs the other waits for, so they share a lane
-  // unless all of them fit the GPU twice over
-  if (!slaunch.empty()) {
-    const DevSlab* ds = b->slabs + (size_t)k * b->slabs_cap;
-    const DevTileInst* dti = b->tinsts + (size_t)k * b->tinsts_cap;
-    hipStream_t st = nullptr;
-    for (size_t l = 0; l < slaunch.size(); ++l) {
-      if (l == 0 || slab_side_by_side) {
-        st = lane_stream(lane);
-        if (fork && lane < kAuxStreams) LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
-        ++lane;
+  // by side could each hold CUs the other waits for, so they share a lane, in
+  // order, unless all of them fit the GPU twice over
+  struct LaneItem { int kind; int idx; double est; };   // kind 0 resident, 1 tiled, 2 slab (-1: the chain)
+  std::vector<LaneItem> items;
+  for (size_t l = 0; l < launches.size(); ++l) {
+    const Launch& L = launches[l];
+    items.push_back({0, (int)l, std::max(L.est_max, L.est_sum / b->lim.cus)});
+  }
+  for (size_t g = 0; g < tgroups.size(); ++g) items.push_back({1, (int)g, tgroups[g].est});
+  if (slab_side_by_side) {
+    for (size_t l = 0; l < slaunch.size(); ++l) items.push_back({2, (int)l, slaunch[l].est});
+  } else if (!slaunch.empty()) {
+    double est = 0.0;
+    for (const SlabLaunch& S : slaunch) est += S.est;
+    items.push_back({2, -1, est});
+  }
+  const bool fork = items.size() > 1;
+  const int nlanes = std::min<int>((int)items.size(), b->lanes > 0 ? b->lanes : hw_lanes());
+  if ((int)items.size() > nlanes)
+    std::stable_sort(items.begin(), items.end(), [](const LaneItem& x, const LaneItem& y) { return x.est > y.est; });
+  std::vector<double> lane_load(nlanes, 0.0);
+  std::vector<char> lane_forked(nlanes, 0);
+  if (fork) LBM_HIP(hipEventRecord(b->fork, b->stream));
+  const DevSlab* ds = b->slabs + (size_t)k * b->slabs_cap;
+  const DevTileInst* dti_all = b->tinsts + (size_t)k * b->tinsts_cap;
+  auto issue_slab = [&](size_t l, hipStream_t st) -> lbm_status {
+    const SlabLaunch& L = slaunch[l];
+    void* b0 = L.prec ? (void*)b->f32[0] : (void*)b->f64[0];
+    void* b1 = L.prec ? (void*)b->f32[1] : (void*)b->f64[1];
+    int* flags = b->sflags + L.foff;
+    LBM_HIP(hipMemsetAsync(flags, 0, sizeof(int) * L.count, st));
+    const int mute = (b->test_stall == 2 && l == 0) ? 0 : -1;
+    LBM_HIP(launch_slab(L.q, L.prec, L.code, ds + L.first, L.count, dti_all, b0, b1, L.s, L.halo,
+                        (unsigned char*)b->xbuf + L.xoff, flags, b->coefs, b->status, wait_ticks(b, L.s), mute,
+                        L.block, L.lds, st));
+    return LBM_OK;
+  };
+  for (size_t ii = 0; ii < items.size(); ++ii) {
+    const LaneItem& it = items[ii];
+    hipStream_t st = b->stream;
+    if (fork) {
+      const int ln = (int)items.size() <= nlanes
+                         ? (int)ii
+                         : (int)(std::min_element(lane_load.begin(), lane_load.end()) - lane_load.begin());
+      lane_load[ln] += it.est;
+      st = b->aux[ln];
+      if (!lane_forked[ln]) {
+        LBM_HIP(hipStreamWaitEvent(st, b->fork, 0));
+        lane_forked[ln] = 1;
       }
-      const SlabLaunch& L = slaunch[l];
-      void* b0 = L.prec ? (void*)b->f32[0] : (void*)b->f64[0];
-      void* b1 = L.prec ? (void*)b->f32[1] : (void*)b->f64[1];
-      int* flags = b->sflags + L.foff;
-      LBM_HIP(hipMemsetAsync(flags, 0, sizeof(int) * L.count, st));
-      const int mute = (b->test_stall == 2 && l == 0) ? 0 : -1;
-      LBM_HIP(launch_slab(L.q, L.prec, L.code, ds + L.first, L.count, dti, b0, b1, L.s, L.halo,
-                          (unsigned char*)b->xbuf + L.xoff, flags, b->coefs, b->status, wait_ticks(b, L.s), mute,
-                          L.block, L.lds, st));
     }
+    if (it.kind == 0) {
+      const int l = it.idx;
+      const Launch& L = launches[l];
+      int per_cu = 0;
+      LBM_HIP(resident_occupancy(L.q, L.prec, L.code, L.block, L.lds, &per_cu));
+      if (per_cu < 1) return LBM_ERR_UNSUPPORTED;
+      int grid = std::min<int>(std::min<int>(L.count, per_cu * b->lim.cus), kMaxResidentGrid);
+      if (b->res_grid > 0) grid = std::min(grid, b->res_grid);
+      // more jobs than workgroups: split the steps into chunks so that each
+      // workgroup takes about kChunkItems items and the launch ends evenly;
+      // chunks keep at least kMinChunkSteps steps (a chunk reloads its state)
+      int nchunks = 1;
+      if (L.count > grid) {
+        nchunks = (int)std::min<int64_t>((kChunkItems * (int64_t)grid + L.count - 1) / L.count,
+                                         std::max<int64_t>(1, L.maxsteps / kMinChunkSteps));
+        nchunks = std::max(1, std::min(nchunks, kMaxChunks));
+      }
+      if (b->res_chunks > 0) nchunks = b->res_chunks;
+      int* slots = b->slots + (size_t)(k * kMaxLaunches + l) * kMaxResidentGrid;
+      int* done = b->done + (size_t)k * b->items_cap + L.first;
+      const long long ticks = wait_ticks(b, L.maxsteps / nchunks + 1);
+      const int stall = (b->test_stall == 1 && l == 0 && nchunks > 1) ? 0 : -1;
+      LBM_HIP(launch_resident(L.q, L.prec, L.code, djobs + L.first, ditems, L.count, nchunks, counters + l, slots,
+                              done, b->coefs, b->status, ticks, stall, grid, L.block, L.lds, st));
+    } else if (it.kind == 1) {
+      const TileGroup& G = tgroups[it.idx];
+      DevTile* dt = b->tiles + (size_t)k * b->tiles_cap + G.first;
+      DevTileInst* dti = b->tinsts + (size_t)k * b->tinsts_cap;
+      void* b0 = G.prec ? (void*)b->f32[0] : (void*)b->f64[0];
+      void* b1 = G.prec ? (void*)b->f32[1] : (void*)b->f64[1];
+      for (int l = 0; l < G.launches; ++l)
+        LBM_HIP(launch_tile(G.q, G.prec, dt, G.ntiles, dti, b0, b1, l, G.s, G.halo, b->coefs, b->status, G.block,
+                            G.lds, st));
+      for (int t = G.tfirst; t < G.tfirst + G.tcount; ++t) {
+        HostInst& h = b->inst[htin[t].inst];
+        const int L = (int)((htin[t].steps + G.s - 1) / G.s);
+        h.cur = htin[t].cur0 ^ (L & 1);
+      }
+    } else if (it.idx >= 0) {
+      lbm_status s = issue_slab((size_t)it.idx, st);
+      if (s != LBM_OK) return s;
+    } else {
+      for (size_t l = 0; l < slaunch.size(); ++l) {
+        lbm_status s = issue_slab(l, st);
+        if (s != LBM_OK) return s;
+      }
+    }
+  }
+  if (!slaunch.empty())
     for (const DevSlab& sl : svec)
       if (sl.x0 == 0) b->inst[htin[sl.ti].inst].cur ^= 1;   // one flip per instance: output in the other buffer
-  }
   if (fork) {
-    const int nst = std::min<int>(lanes, kAuxStreams);
-    for (int a = 0; a < nst; ++a) {
+    for (int a = 0; a < nlanes; ++a) {
+      if (!lane_forked[a]) continue;
       LBM_HIP(hipEventRecord(b->join[a], b->aux[a]));
       LBM_HIP(hipStreamWaitEvent(b->stream, b->join[a], 0));
     }
@@ -1891,6 +1954,12 @@ lbm_status lbm_batch_set_resident(lbm_batch b, int32_t max_workgroups, int32_t c
     return LBM_ERR_INVALID_ARG;
   b->res_grid = max_workgroups;
   b->res_chunks = chunks;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_lanes(lbm_batch b, int32_t lanes) {
+  if (!b || lanes < 0 || lanes > kAuxStreams) return LBM_ERR_INVALID_ARG;
+  b->lanes = lanes;
   return LBM_OK;
 }
 

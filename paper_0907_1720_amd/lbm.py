@@ -147,6 +147,7 @@ def library() -> ctypes.CDLL:
         "lbm_batch_set_path": (I32, [P, I32]),
         "lbm_batch_set_tiling": (I32, [P, I32, I32]),
         "lbm_batch_set_resident": (I32, [P, I32, I32]),
+        "lbm_batch_set_lanes": (I32, [P, I32]),
         "lbm_batch_autotune": (I32, [P, I64, P]),
         "lbm_batch_test_stall": (I32, [P, I32, I64]),
         "lbm_batch_destroy": (I32, [P]),
@@ -470,6 +471,10 @@ class Batch:
     def set_resident(self, max_workgroups: int = 0, chunks: int = 0):
         _check(library().lbm_batch_set_resident(self._h, int(max_workgroups), int(chunks)),
                "lbm_batch_set_resident")
+
+    def set_lanes(self, lanes: int = 0):
+        """Streams one advance spreads its launches over (0 = one per hardware queue, at most 16)."""
+        _check(library().lbm_batch_set_lanes(self._h, int(lanes)), "lbm_batch_set_lanes")
 
     def test_stall(self, what: int, wait_us: int = 0):
         """Forces a bounded device wait to give up (test hook; 0, 0 restores)."""

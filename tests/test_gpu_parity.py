@@ -315,6 +315,36 @@ def test_batch_instance_alone_equals_in_mix():
     b.close()
 
 
+def test_launch_lanes_bitwise():
+    """A few mixed instances (the serving mix: D1Q5 and D1Q7 variants, FP32 and
+    FP64, N up to 16384) make a pass of many small launches -- resident jobs
+    per variant and, the GPU being mostly idle, narrow slabs per variant side
+    by side.  Spread over 1, 2, 3 or 16 streams (longest estimated launch
+    first to the least loaded stream once there are more launches than
+    streams), every instance ends bit for bit the same."""
+    reqs = [W.serving_request(i, steps_max=3000) for i in range(20)]
+    steps = [r.steps for r in reqs]
+    say("  launch lanes: N", [r.problem.n for r in reqs], "steps", steps)
+    out = {}
+    for lanes in (0, 1, 2, 3, 16):
+        b = lbm.Batch([r.problem for r in reqs])
+        b.set_lanes(lanes)
+        b.load_phi([r.phi0 for r in reqs])
+        b.advance(steps)
+        out[lanes] = [b.read_phi(k) for k in range(len(reqs))]
+        b.close()
+        say("  lanes", lanes, "done")
+    for lanes in (1, 2, 3, 16):
+        for k in range(len(reqs)):
+            assert np.array_equal(out[lanes][k][0], out[0][k][0]), (lanes, k)
+            assert out[lanes][k][1] == out[0][k][1] == lbm.OK, (lanes, k)
+    b = lbm.Batch([reqs[0].problem])
+    for bad in (-1, 17):
+        with pytest.raises(lbm.LBMError):
+            b.set_lanes(bad)
+    b.close()
+
+
 @pytest.mark.parametrize("prec", [W.F64, W.F32_DEV])
 def test_resident_step_chunks_bitwise(prec):
     """Splitting each job's steps into chunks (each chunk reloads and writes
