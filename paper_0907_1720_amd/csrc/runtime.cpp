@@ -590,12 +590,18 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   // leaves most CUs idle; its step time is that of its largest instances, one
   // CU each.  There, instances of kSplitNodes nodes or more are split into
   // narrow slabs (an eighth of an LDS) spread over otherwise idle CUs.
-  size_t res_bytes = 0;
-  for (int i = 0; i < count; ++i)
-    if (steps[i] && b->path == 0 && fits_resident(b, b->inst[i]))
-      res_bytes += (size_t)lds_stride(b->inst[i].q) * b->inst[i].n * elem_size(b->inst[i]);
-  const bool latency = b->path == 0 && b->res_grid == 0 && 4 * res_bytes < (size_t)b->lim.cus * b->lim.lds_max;
-  const int slab_wgs = b->tile_wgs > 0 ? b->tile_wgs : 2;
+  // The same holds for instances beyond one LDS when all the pass's state is
+  // that small (a serving round): their slabs are narrow too.
+  size_t res_bytes = 0, all_bytes = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!steps[i] || b->path != 0) continue;
+    const size_t by = (size_t)lds_stride(b->inst[i].q) * b->inst[i].n * elem_size(b->inst[i]);
+    all_bytes += by;
+    if (fits_resident(b, b->inst[i])) res_bytes += by;
+  }
+  const size_t lds_all = (size_t)b->lim.cus * b->lim.lds_max;
+  const bool latency = b->path == 0 && b->res_grid == 0 && 4 * res_bytes < lds_all;
+  const int slab_wgs = b->tile_wgs > 0 ? b->tile_wgs : latency && 4 * all_bytes < lds_all ? 8 : 2;
   for (int i = 0; i < count; ++i) {
     if (steps[i] == 0) continue;
     const HostInst& h = b->inst[i];
