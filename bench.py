@@ -153,6 +153,17 @@ def algorithmic_flops_power_sum(nu: np.ndarray, G: np.ndarray) -> int:
     return flops + 2 * q
 
 
+def serving_knee(sweep, frac: float = 0.8):
+    """The first arrival rate of a serving sweep at which the work finished
+    while the arrivals lasted falls below `frac` of the work arriving.  The
+    drain after the last arrival (a few tenths of a second for the largest
+    requests) is not counted: it would put every rate near 80% of a 1.5 s
+    window.  What the largest requests still have to do when the arrivals end
+    is up to ~15% of the window's work below saturation, hence 80%."""
+    return next((r["rate_per_s"] for r in sweep
+                 if (r["window_node_updates_per_s"] or 0) < frac * (r["offered_node_updates_per_s"] or 0)), None)
+
+
 def _oracle_one(args):
     i, steps = args
     from oracle import lbm_oracle as O
@@ -548,14 +559,7 @@ def main():
                                             "node_updates_per_s", "window_node_updates_per_s", "wall_s",
                                             "p50_latency_s", "p99_latency_s",
                                             "mean_queue_wait_s", "p99_queue_wait_s", "p50_service_s", "nonfinite")})
-        # knee: the first rate at which the work finished while the arrivals
-        # last falls below 80% of the work arriving.  The drain after the last
-        # arrival (a few tenths of a second for the largest requests) is not
-        # counted: it would put every rate near 80% of a 1.5 s window.  What
-        # the largest requests still have to do when the arrivals end is: up
-        # to ~15% of the window's work below saturation, hence 80%.
-        knee = next((s_["rate_per_s"] for s_ in sweep
-                     if (s_["window_node_updates_per_s"] or 0) < 0.8 * (s_["offered_node_updates_per_s"] or 0)), None)
+        knee = serving_knee(sweep)
         out = {"workload": "Poisson arrivals of the 7-family request mix (N log-uniform [128, 16384], steps "
                            "log-uniform [1e3, 1e5], FP32 / FP64), " f"{args.serve_window} s of arrivals per rate "
                            "(at least 64 requests), non-blocking rounds (lbm_server_pump)",
