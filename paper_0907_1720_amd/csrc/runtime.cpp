@@ -784,10 +784,10 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
   // be narrower than a halo, goes to temporal blocking instead.  When a
   // group's instances need several launches, their steps are split into
   // chunks and the (instance, chunk) items fill the launches in chunk-major
-  // order: every launch but the last is full, and the last one is short only
-  // by part of a chunk (without chunks, a last launch with a few instances
-  // costs a whole launch's time).  An instance's chunk c + 1 always lies in a
-  // later launch than its chunk c, which the lane's order serialises.
+  // order, an even share each (without chunks, a last launch with a few
+  // instances costs a whole launch's time).  An instance's chunk c + 1 always
+  // lies in a later launch than its chunk c (a launch holds less than one
+  // chunk's items plus one instance), which the lane's order serialises.
   struct SlabLaunch { int q; int prec; int code; int first, count, cap, s, halo, block; size_t lds; size_t xoff; int foff; double est; };
   std::vector<SlabLaunch> slaunch;
   std::vector<DevSlab> svec;
@@ -846,20 +846,20 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       // so c chunks cost (launches needed for c chunks) / c; take the fewest
       // chunks (at most 8, each >= kMinSlabChunk steps) within 3% of the
       // cheapest, counting launches by packing whole instances as below
+      auto launches_for = [&](int c) {
+        int nl = 1, fill = 0;
+        for (int r = 0; r < c; ++r)
+          for (const auto& m : mem) {
+            if (fill + m.second > capacity) {
+              ++nl;
+              fill = 0;
+            }
+            fill += m.second;
+          }
+        return nl;
+      };
       int nch = 1;
       if (total > capacity && maxsteps >= 2 * kMinSlabChunk) {
-        auto launches_for = [&](int c) {
-          int nl = 1, fill = 0;
-          for (int r = 0; r < c; ++r)
-            for (const auto& m : mem) {
-              if (fill + m.second > capacity) {
-                ++nl;
-                fill = 0;
-              }
-              fill += m.second;
-            }
-          return nl;
-        };
         double best = 1e30;
         std::vector<double> cost(9, 1e30);
         for (int c = 1; c <= 8 && maxsteps / c >= kMinSlabChunk; ++c) {
@@ -872,6 +872,12 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
             break;
           }
       }
+      // the items spread evenly over that many launches (a launch is closed
+      // once it holds its share), so that no launch is a short tail: the
+      // packing above would fill all but the last, which, lightly loaded, runs
+      // its steps faster but still about as long as a full one
+      const int64_t share = total * nch > capacity ? (total * nch + launches_for(nch) - 1) / launches_for(nch)
+                                                   : capacity;
       for (int c = 0; c < nch; ++c) {
         for (const auto& [i, ks] : mem) {
           const HostInst& h = b->inst[i];
@@ -879,7 +885,7 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
           const int64_t st = base + (c < rem ? 1 : 0);
           if (st == 0) continue;
           const int core = (h.n + ks - 1) / ks;
-          if (L.count + ks > capacity) {
+          if (L.count + ks > capacity || L.count >= share) {
             slaunch.push_back(L);
             L.first = (int)svec.size();
             L.count = 0;
