@@ -132,6 +132,19 @@ __host__ __device__ constexpr int opposite(int j) {
 // -omega f_rest like the odd tables).
 __device__ __forceinline__ double fma_a(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_a(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// a * b + c with c a wave-uniform value in scalar registers, as one VOP3 FMA
+// with a scalar operand (the compiler otherwise copies c to vector registers
+// to use the two-address form)
+__device__ __forceinline__ double fma_s(double a, double b, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+#else
+  return __builtin_fma(a, b, c);
+#endif
+}
+__device__ __forceinline__ float fma_s(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 template <int D, int P, typename A>
 __device__ __forceinline__ A poly_eval(const A* __restrict__ c, A p) {
@@ -197,6 +210,17 @@ struct Relaxer {
     return 1;
   }
   static constexpr int kNV = nv_for_table();
+  // Tables too large for either scheme (a dense degree-13 D1Q7 table in FP64:
+  // 7 x 13 x 2 words below the top coefficients) are read from the constant
+  // cache at every update, a population at a time (dense tables only): held
+  // across the node loop they spilled to vector-register lanes, two lane reads
+  // per FMA (213 VALU instructions per node in the D1Q7 degree-13 loop, 107
+  // now).
+  static constexpr bool kReload =
+      V && P < 2 && !kPin && kNV == 1 && Q * (K - 1) * (int)sizeof(A) / 4 > 70;
+  using CT = const __attribute__((address_space(4))) A*;
+  // coefficients loaded together: a population's, at most 13
+  static constexpr int kGroup = K - 1 < 13 ? (K - 1 > 0 ? K - 1 : 1) : 13;
   const A* __restrict__ c;   // [Q][kRow]: dense, or the odd degrees compacted
   const DevCoef* __restrict__ cfp;   // power-sum tables (P = 2)
   A top[Q];
@@ -327,6 +351,26 @@ struct Relaxer {
         const double acc = __builtin_fma(b1, a1, b0 * a0);
         const double add = sizeof(T) == 4 ? cst[j] : 0.0;
         f[j] = (T)__builtin_fma((double)w0, (double)f[j], acc + add);
+      }
+    } else if constexpr (P == 0 && kReload) {
+      // the coefficients in groups of kGroup, in the order of use, as scalar
+      // operands of the FMAs; the loads of group g + 1 may not start before
+      // group g - 1 has ended (two pointers that the compiler must treat as
+      // new after every other group), so at most two groups are live
+      CT pt[2] = {(CT)c, (CT)c};
+      int u = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        A acc = top[j];
+#pragma unroll
+        for (int d = K - 2; d >= 0; --d, ++u) {
+          acc = fma_s(acc, p, pt[(u / kGroup) & 1][j * kRow + d]);
+#if defined(__HIP_DEVICE_COMPILE__)
+          // device pass only: a register class of the GPU
+          if (u % kGroup == kGroup - 1) asm volatile("" : "+s"(pt[(u / kGroup) & 1]) : "v"(acc));
+#endif
+        }
+        f[j] = (T)fma_a(w0, (A)f[j], acc);
       }
     } else if constexpr (P == 0) {
 #pragma unroll
