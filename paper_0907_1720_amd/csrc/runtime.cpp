@@ -662,8 +662,13 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       const int vgprs = std::max(1, resident_vgprs(q, pr, code));
       const int cu_waves = 4 * std::max(1, std::min(8, 512 / vgprs));
       const int jobs_per_cu = std::max<int>(1, (int)(b->lim.lds_max / cap));
-      // (bounded kernels are compiled for workgroups of at most 512 threads)
-      const int kJobWaves = std::max(1, std::min(bnd ? 8 : 16, cu_waves / jobs_per_cu));
+      // waves per job: the CU's waves shared by the jobs it holds at once -- in
+      // the latency regime (one job per instance) with no more instances than
+      // CUs, one job per CU (a 256-tau sweep of bounded instances gets twice the
+      // waves).  (bounded kernels are compiled for workgroups of at most 512
+      // threads)
+      const int cu_jobs = latency && (int)g.size() <= b->lim.cus ? 1 : jobs_per_cu;
+      const int kJobWaves = std::max(1, std::min(bnd ? 8 : 16, cu_waves / cu_jobs));
       // a pass that leaves most CUs idle (latency regime) gives every instance a
       // job of its own and up to a wave per 64 nodes: its steps end sooner
       const int kNodesPerWave = latency ? 64 : 128;
