@@ -536,6 +536,36 @@ def test_random_sixth_order_equation():
         assert maxerr(got, want) <= FP64_TOL
 
 
+@pytest.mark.parametrize("prec", [W.F64, W.F32_DEV])
+@pytest.mark.parametrize("n", [300, 1500, 5000])
+def test_random_sixth_order_every_path_bitwise(n, prec):
+    """The degree-13 D1Q7 equilibrium of the random sixth-order equation (its
+    table read per update from the constant cache by the resident and slab
+    kernels) gives the same bits on every kernel path, alone and in a small
+    mixed batch, and the FP64 result matches the oracle."""
+    g = W.rng(5, 1)
+    p = dataclasses.replace(W.random_m6_problem(g, n), prec=prec, tau=3.0)
+    x = np.arange(n) / n
+    phi0 = 0.3 * np.sin(2 * np.pi * x) + 0.1 * np.cos(6 * np.pi * x + 0.7)
+    steps = 150
+    say("case random m6 paths", n, prec)
+    ref = gpu_run(p, phi0, steps, lbm.PATH_STREAM)
+    for path in (lbm.PATH_RESIDENT, lbm.PATH_TILED, lbm.PATH_SLAB, lbm.PATH_AUTO):
+        if path == lbm.PATH_RESIDENT and 7 * n * (8 if prec == W.F64 else 4) > LDS_BYTES:
+            continue
+        got = gpu_run(p, phi0, steps, path)
+        assert np.array_equal(got, ref), path
+    others = [W.config2_instance(k, prec=prec) for k in range(3)]
+    b = lbm.Batch([p] + [o.problem for o in others])
+    b.load_phi([phi0] + [o.phi0 for o in others])
+    b.advance([steps, 40, 50, 60])
+    mix, st = b.read_phi(0)
+    b.close()
+    assert st == lbm.OK and np.array_equal(mix, ref)
+    if prec == W.F64 and n <= 1500:
+        assert maxerr(ref, O.run(p, phi0, steps)) <= FP64_TOL
+
+
 # ---------------------------------------------------------------------------
 # read-outs, checkpoint/resume, failure isolation, caller-owned memory
 # ---------------------------------------------------------------------------
