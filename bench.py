@@ -43,6 +43,9 @@ Reported:
   cpu_baseline          the CPU oracle on a sample of the same instances
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+The process runs with GPU_MAX_HW_QUEUES = 16 (--hw-queues; HIP's default is 4): the
+library spreads a pass's launches over one stream per hardware queue.
 """
 import argparse
 import dataclasses
