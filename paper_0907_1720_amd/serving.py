@@ -77,9 +77,11 @@ def run_poisson(server: "lbm.Server", requests: Sequence, rate: float, seed: int
                 if keep_results:
                     results[i] = res[0]
         if running:
-            # the round is on the device: wait a little, or until the next arrival
+            # the round is on the device: wait a little (50 us: the GPU idles from
+            # a round's end until the next pump launches the next one), or until
+            # the next arrival
             nxt_t = arrivals[nxt] - (time.perf_counter() - t0) if nxt < len(requests) else 1e-3
-            time.sleep(max(0.0, min(2e-4, nxt_t)))
+            time.sleep(max(0.0, min(5e-5, nxt_t)))
     wall = time.perf_counter() - t0
     nu1, ms1, _ = server.stats()
     span = float(arrivals[-1]) if len(arrivals) > 1 else 0.0
