@@ -672,7 +672,24 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
       // a pass that leaves most CUs idle (latency regime) gives every instance a
       // job of its own and up to a wave per 64 nodes: its steps end sooner
       const int kNodesPerWave = latency ? 64 : 128;
-      struct Bin { int64_t steps; int variant; size_t bytes; std::vector<int> members; };
+      // Passes per step of a full job: a job's waves sweep its nodes 64 per
+      // pass, and a member of n nodes needs ceil(n / (64 passes)) waves to end
+      // its sweep within that many passes.  Packed by bytes alone, a job's
+      // members can need more waves than the job has, so some waves take a
+      // pass more than the rest and every step waits for them.  Where two jobs
+      // share each CU (eight waves per SIMD: the step is bound by VALU issue) a
+      // job therefore admits a member only while the members' waves at that
+      // pass count fit (the 4096-instance FP32 batch: 46.5 -> 45.3 ms).  One
+      // job per CU is bound by the step's latency instead, and fuller jobs pay
+      // there (the FP64 batch ran 1.5% slower with the rule).
+      const bool wave_budget = !latency && jobs_per_cu >= 2;
+      const int full_passes = std::max<int>(
+          std::max(1, kNodesPerWave / 64),
+          (int)((cap / ((size_t)lds_stride(q) * es) + 64 * (size_t)kJobWaves - 1) / (64 * (size_t)kJobWaves)));
+      auto waves_at = [&](int i) {
+        return wave_budget ? (b->inst[i].n + 64 * full_passes - 1) / (64 * full_passes) : 0;
+      };
+      struct Bin { int64_t steps; int variant; size_t bytes; int waves; std::vector<int> members; };
       std::vector<Bin> bins;
       auto pack = [&](int max_inst) {
         bins.clear();
@@ -683,13 +700,15 @@ lbm_status advance_pass(lbm_batch_s* b, const int64_t* steps) {
           bool placed = false;
           for (size_t u = open_from; u < bins.size() && !placed; ++u) {
             Bin& bn = bins[u];
-            if (bn.bytes + bytes_of(i) <= cap && (int)bn.members.size() < max_inst) {
+            if (bn.bytes + bytes_of(i) <= cap && (int)bn.members.size() < max_inst &&
+                bn.waves + waves_at(i) <= kJobWaves) {
               bn.bytes += bytes_of(i);
+              bn.waves += waves_at(i);
               bn.members.push_back(i);
               placed = true;
             }
           }
-          if (!placed) bins.push_back(Bin{steps[i], b->inst[i].D, bytes_of(i), {i}});
+          if (!placed) bins.push_back(Bin{steps[i], b->inst[i].D, bytes_of(i), waves_at(i), {i}});
         }
       };
       pack(latency ? 1 : std::min(kMaxJobInstances, kJobWaves));
